@@ -1,0 +1,368 @@
+/*
+ * ORACLE -- test infrastructure, not part of the product.
+ *
+ * A plain, slow, scalar FP64 tracker used only to check the GPU path: only the
+ * test suite, the smoke check and the benchmark's CPU-baseline leg may build,
+ * load or call it.  It shares no code, header, table or constant with the HIP
+ * library; the two are written independently from the same description.
+ *
+ * What it computes (the paper, Introduction and Methods "MODPATH"): each
+ * particle is displaced through the flow-model cells one cell at a time, a
+ * whole cell in a single semi-analytical step up to a cell interface, and is
+ * then handed to the neighbour across that interface, until a stopping
+ * condition is met (a boundary face, the maximum tracking time, or a cell with
+ * sink flows).  Particles are independent of one another.  The paper defers
+ * the per-cell mathematics to Pollock's semi-analytical method; it is written
+ * out here from the ODE it solves exactly:
+ *
+ *   inside a cell, each velocity component is the linear interpolation between
+ *   its two face velocities, u(xi) = u1 + A*xi with u = Q / (n * V) in local
+ *   units (1/d) and A = u2 - u1.  The components separate, so
+ *   dxi/dt = u1 + A*xi has the closed-form solution
+ *      xi(tau) = xi + u_p * tau * psi(A*tau),  psi(y) = expm1(y)/y, psi(0) = 1,
+ *   and the time to reach face xi_e (velocity u_e) is
+ *      dt = ln(u_e / u_p) / A = (D/u_p) * phi(A*D/u_p),  D = xi_e - xi,
+ *      phi(x) = log1p(x)/x, phi(0) = 1   (dt = D/u_p when A = 0).
+ *
+ * Steps per particle, in order (state: cell c, local xi/eta/zeta, time t):
+ *   S0 release checks; S1 cell velocities; S2 per-axis exit feasibility;
+ *   S3 per-axis exit time; S4 earliest face; S5 time limit; S6 advance;
+ *   S7 transfer to the neighbour and stop checks; S8 timeseries positions.
+ * Readings where the paper is silent (tie-break, clamping, sink and time-limit
+ * semantics, snapshot semantics, path hash) are stated next to each step.
+ *
+ * Statuses: 0 ACTIVE, 1 BOUNDARY, 2 SINK, 3 MAX_TIME, 4 STEP_CAP, 5 STRANDED,
+ * 6 INVALID_START, 7 INACTIVE_NEIGHBOR.
+ * Build: gcc -O2 -fno-fast-math -ffp-contract=off (no FMA contraction).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#define ST_ACTIVE 0
+#define ST_BOUNDARY 1
+#define ST_SINK 2
+#define ST_MAX_TIME 3
+#define ST_STEP_CAP 4
+#define ST_STRANDED 5
+#define ST_INVALID_START 6
+#define ST_INACTIVE_NEIGHBOR 7
+
+#define CELL_ACTIVE 1
+#define CELL_SINK 2
+
+typedef struct {
+    int32_t nx, ny, nz;
+    double dx, dy, dz, x0, y0, z0;
+    const double* qx;        /* [nz][ny][nx+1], + = +i */
+    const double* qy;        /* [nz][ny+1][nx], + = +j */
+    const double* qz;        /* [nz+1][ny][nx], + = +k */
+    const double* porosity;  /* [nz][ny][nx] or NULL */
+    double porosity_scalar;
+    const int32_t* flags;    /* [nz][ny][nx] */
+} oracle_grid;
+
+typedef struct {
+    int32_t direction;       /* +1 forward, -1 backward */
+    double t_max;
+    int64_t max_steps;
+    int32_t stop_at_sink;
+    const double* snap_times;  /* ascending, or NULL */
+    int32_t n_snap;
+    double* snap_xyz;          /* [n][n_snap][3] or NULL */
+    double* out_xyz;           /* [n][3] or NULL */
+    int32_t path_cap;          /* per-particle capacity of the path record, 0 = none */
+    int32_t* path_cell;        /* [n][path_cap] cell left at each crossing */
+    int32_t* path_face;        /* [n][path_cap] 2*axis + (1 if the high face) */
+    double* path_t;            /* [n][path_cap] time at the crossing */
+    double* path_xyz;          /* [n][path_cap][3] global position on the face */
+    int32_t n_threads;
+} oracle_opts;
+
+/* One axis of the cell: face velocities u1 (low face) and u2 (high face). */
+typedef struct {
+    double u1, u2;
+} axis_vel;
+
+/* S6 formula: position along one axis after time tau, clamped to [0,1]. */
+static double advance(axis_vel v, double xi, double tau) {
+    double A = v.u2 - v.u1;
+    double up = v.u1 + A * xi;
+    if (up == 0.0) return xi;
+    double y = A * tau;
+    double psi = (y == 0.0) ? 1.0 : expm1(y) / y;
+    double xn = xi + (up * tau) * psi;
+    if (xn < 0.0) xn = 0.0;
+    if (xn > 1.0) xn = 1.0;
+    return xn;
+}
+
+/*
+ * S2 + S3: time for one axis to reach its exit face, +INFINITY if it cannot.
+ * The candidate face is the one the velocity points to; it is reached only
+ * if the face velocity has the same strict sign as the particle velocity
+ * (a linear u cannot change sign without passing through zero, and a face
+ * with zero or opposite velocity is approached asymptotically).
+ */
+static double axis_exit_time(axis_vel v, double xi, double* xi_exit) {
+    double A = v.u2 - v.u1;
+    double up = v.u1 + A * xi;
+    double ue;
+    if (up > 0.0) {
+        *xi_exit = 1.0;
+        ue = v.u2;
+        if (!(ue > 0.0)) return INFINITY;
+    } else if (up < 0.0) {
+        *xi_exit = 0.0;
+        ue = v.u1;
+        if (!(ue < 0.0)) return INFINITY;
+    } else {
+        return INFINITY;
+    }
+    double D = *xi_exit - xi;
+    double r = D / up;
+    double x = A * r;
+    double dt;
+    if (x == 0.0) {
+        dt = r;
+    } else if (x < -0.5) {
+        /* strongly decelerating: the ratio u_e/u_p is formed exactly enough,
+         * 1 + x would lose digits */
+        dt = log(ue / up) / A;
+    } else {
+        dt = r * (log1p(x) / x);
+    }
+    if (dt < 0.0) dt = 0.0;
+    return dt;
+}
+
+static void global_xyz(const oracle_grid* g, int64_t c, double xi, double eta, double zeta,
+                       double* out) {
+    int64_t plane = (int64_t)g->nx * g->ny;
+    int64_t k = c / plane;
+    int64_t rem = c - k * plane;
+    int64_t j = rem / g->nx;
+    int64_t i = rem - j * g->nx;
+    out[0] = g->x0 + ((double)i + xi) * g->dx;
+    out[1] = g->y0 + ((double)j + eta) * g->dy;
+    out[2] = g->z0 + ((double)k + zeta) * g->dz;
+}
+
+static void put_nan3(double* p) {
+    p[0] = NAN;
+    p[1] = NAN;
+    p[2] = NAN;
+}
+
+/*
+ * S8: positions at every snapshot time s with from <= s < to (or s <= to
+ * when closed), evaluated from the state at the start of the current step
+ * (time t, coordinates loc) with tau = s - t.  *next is the first snapshot
+ * not yet written.
+ */
+static void snapshots(const oracle_grid* g, const oracle_opts* o, double* row, int32_t* next,
+                      int64_t c, const axis_vel* v, const double* loc, double t, double to,
+                      int closed) {
+    while (*next < o->n_snap) {
+        double s = o->snap_times[*next];
+        if (closed ? !(s <= to) : !(s < to)) break;
+        double tau = s - t;
+        double a = advance(v[0], loc[0], tau);
+        double b = advance(v[1], loc[1], tau);
+        double d = advance(v[2], loc[2], tau);
+        global_xyz(g, c, a, b, d, row + 3 * (int64_t)(*next));
+        ++*next;
+    }
+}
+
+static void snapshots_nan(const oracle_opts* o, double* row, int32_t* next) {
+    while (*next < o->n_snap) {
+        put_nan3(row + 3 * (int64_t)(*next));
+        ++*next;
+    }
+}
+
+static void track_one(const oracle_grid* g, const oracle_opts* o, int64_t p, int32_t* cell_,
+                      double* xi_, double* eta_, double* zeta_, double* t_, int32_t* status_,
+                      int32_t* ncross_, uint64_t* hash_) {
+    const int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
+    const int64_t plane = (int64_t)g->nx * g->ny;
+    double* row = (o->snap_xyz && o->n_snap > 0) ? o->snap_xyz + (int64_t)p * o->n_snap * 3 : NULL;
+    int32_t st = status_[p];
+    if (st != ST_ACTIVE && st != ST_MAX_TIME) return; /* already terminated: left as is */
+    const int fresh = (st == ST_ACTIVE);
+
+    int64_t c = cell_[p];
+    double loc[3] = {xi_[p], eta_[p], zeta_[p]};
+    double t = t_[p];
+    int32_t ncross = ncross_[p];
+    uint64_t hash = hash_[p];
+    int32_t npath = 0;
+
+    /* S0: release checks */
+    int bad = (c < 0 || c >= ncell);
+    if (!bad) bad = !(g->flags[c] & CELL_ACTIVE);
+    for (int a = 0; a < 3; ++a)
+        if (!(loc[a] >= 0.0 && loc[a] <= 1.0)) bad = 1;
+    if (!(t == t) || isinf(t)) bad = 1;
+    if (bad) {
+        status_[p] = ST_INVALID_START;
+        if (row) {
+            int32_t k0 = 0;
+            snapshots_nan(o, row, &k0);
+        }
+        return;
+    }
+    int32_t next = 0;
+    if (row) {
+        /* snapshots before the release of a fresh particle are undefined;
+         * a resumed particle keeps what earlier calls wrote */
+        while (next < o->n_snap && o->snap_times[next] < t) {
+            if (fresh) put_nan3(row + 3 * (int64_t)next);
+            ++next;
+        }
+    }
+    if ((g->flags[c] & CELL_SINK) && o->stop_at_sink) {
+        status_[p] = ST_SINK;
+        if (row) snapshots_nan(o, row, &next);
+        return;
+    }
+    if (t > o->t_max) {
+        status_[p] = ST_MAX_TIME;
+        if (row) snapshots_nan(o, row, &next);
+        return;
+    }
+
+    const double V = (g->dx * g->dy) * g->dz;
+    const double sgn = o->direction < 0 ? -1.0 : 1.0;
+    for (;;) {
+        /* S1: cell initialisation -- face flows to face velocities */
+        int64_t k = c / plane;
+        int64_t rem = c - k * plane;
+        int64_t j = rem / g->nx;
+        int64_t i = rem - j * g->nx;
+        double n_c = g->porosity ? g->porosity[c] : g->porosity_scalar;
+        double d = n_c * V;
+        double qxl = g->qx[(k * g->ny + j) * (g->nx + 1) + i];
+        double qxh = g->qx[(k * g->ny + j) * (g->nx + 1) + i + 1];
+        double qyl = g->qy[(k * (g->ny + 1) + j) * g->nx + i];
+        double qyh = g->qy[(k * (g->ny + 1) + j + 1) * g->nx + i];
+        double qzl = g->qz[(k * g->ny + j) * g->nx + i];
+        double qzh = g->qz[((k + 1) * g->ny + j) * g->nx + i];
+        axis_vel v[3];
+        v[0].u1 = (sgn * qxl) / d;
+        v[0].u2 = (sgn * qxh) / d;
+        v[1].u1 = (sgn * qyl) / d;
+        v[1].u2 = (sgn * qyh) / d;
+        v[2].u1 = (sgn * qzl) / d;
+        v[2].u2 = (sgn * qzh) / d;
+
+        /* S2-S4: earliest feasible face; exact ties go to the lowest axis */
+        double dt = INFINITY;
+        int axis = -1;
+        double xe = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double e = 0.0;
+            double ta = axis_exit_time(v[a], loc[a], &e);
+            if (ta < dt) {
+                dt = ta;
+                axis = a;
+                xe = e;
+            }
+        }
+
+        /* S5: time limit (strict: a face reached exactly at t_max is crossed) */
+        if (axis < 0 && isinf(o->t_max)) {
+            status_[p] = ST_STRANDED;
+            if (row) snapshots(g, o, row, &next, c, v, loc, t, INFINITY, 1);
+            break;
+        }
+        double t_exit = t + dt;
+        if (t_exit > o->t_max) {
+            double tau = o->t_max - t;
+            if (row) snapshots(g, o, row, &next, c, v, loc, t, o->t_max, 1);
+            for (int a = 0; a < 3; ++a) loc[a] = advance(v[a], loc[a], tau);
+            t = o->t_max;
+            status_[p] = axis < 0 ? ST_STRANDED : ST_MAX_TIME;
+            if (row) snapshots_nan(o, row, &next);
+            break;
+        }
+
+        /* S6: advance to the exit face */
+        if (row) snapshots(g, o, row, &next, c, v, loc, t, t_exit, 0);
+        for (int a = 0; a < 3; ++a)
+            loc[a] = (a == axis) ? xe : advance(v[a], loc[a], dt);
+        t = t_exit;
+        ncross += 1;
+        hash = (hash ^ (uint64_t)(uint32_t)c) * 0x100000001b3ULL;
+        if (o->path_cap > 0 && npath < o->path_cap) {
+            int64_t q = (int64_t)p * o->path_cap + npath;
+            o->path_cell[q] = (int32_t)c;
+            o->path_face[q] = 2 * axis + (xe == 1.0 ? 1 : 0);
+            o->path_t[q] = t;
+            global_xyz(g, c, loc[0], loc[1], loc[2], o->path_xyz + 3 * q);
+            ++npath;
+        }
+
+        /* S7: transfer to the neighbour across the exit face */
+        int64_t ii = i, jj = j, kk = k;
+        int step = (xe == 1.0) ? 1 : -1;
+        if (axis == 0) ii += step;
+        else if (axis == 1) jj += step;
+        else kk += step;
+        if (ii < 0 || ii >= g->nx || jj < 0 || jj >= g->ny || kk < 0 || kk >= g->nz) {
+            status_[p] = ST_BOUNDARY;
+            break;
+        }
+        int64_t cn = (kk * g->ny + jj) * g->nx + ii;
+        if (!(g->flags[cn] & CELL_ACTIVE)) {
+            status_[p] = ST_INACTIVE_NEIGHBOR;
+            break;
+        }
+        c = cn;
+        loc[axis] = 1.0 - xe;
+        if ((g->flags[c] & CELL_SINK) && o->stop_at_sink) {
+            status_[p] = ST_SINK;
+            break;
+        }
+        if (ncross >= o->max_steps) {
+            status_[p] = ST_STEP_CAP;
+            break;
+        }
+    }
+    int32_t fs = status_[p];
+    if (row && (fs == ST_BOUNDARY || fs == ST_SINK || fs == ST_STEP_CAP || fs == ST_INACTIVE_NEIGHBOR))
+        snapshots_nan(o, row, &next);
+
+    cell_[p] = (int32_t)c;
+    xi_[p] = loc[0];
+    eta_[p] = loc[1];
+    zeta_[p] = loc[2];
+    t_[p] = t;
+    ncross_[p] = ncross;
+    hash_[p] = hash;
+}
+
+/* Track particles [0, n) in place.  Returns 0, or -1 on a bad argument. */
+int oracle_track(const oracle_grid* g, const oracle_opts* o, int64_t n, int32_t* cell, double* xi,
+                 double* eta, double* zeta, double* t, int32_t* status, int32_t* ncross,
+                 uint64_t* hash) {
+    if (!g || !o || n < 0 || g->nx <= 0 || g->ny <= 0 || g->nz <= 0) return -1;
+    if (n == 0) return 0;
+    if (!cell || !xi || !eta || !zeta || !t || !status || !ncross || !hash) return -1;
+    if (o->snap_xyz && (o->n_snap < 0 || (o->n_snap > 0 && !o->snap_times))) return -1;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64) num_threads(o->n_threads > 0 ? o->n_threads : 1)
+#endif
+    for (int64_t p = 0; p < n; ++p) {
+        track_one(g, o, p, cell, xi, eta, zeta, t, status, ncross, hash);
+        if (o->out_xyz) {
+            int64_t c = cell[p];
+            if (status[p] == ST_INVALID_START || c < 0 || c >= (int64_t)g->nx * g->ny * g->nz)
+                put_nan3(o->out_xyz + 3 * p);
+            else
+                global_xyz(g, c, xi[p], eta[p], zeta[p], o->out_xyz + 3 * p);
+        }
+    }
+    return 0;
+}
