@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Benchmark: particle cell-crossings per second on one MI355X.
+
+One step = one pass of the whole tracking path over one batch: restore the
+released particle state (device-to-device copy), track every particle to its
+stopping condition through the C ABI (pt_track: counter reset + tracking
+kernel), and read the run summary (pt_results).  Grids and particles are
+resident in HBM before the timed region starts.
+
+Default workload (C2): 100x100x10 cells of 10x10x2 m, lognormal K with
+geometric mean 10 m/d, sigma^2 = 1, correlation length 5 cells, heads 10/0 m
+west/east, porosity 0.3; 1e6 particles released uniformly in the 10 western
+columns; endpoint mode, FP64, persistent work-queue kernel, packed cell
+records, hipGraph launch.  The same steps are also timed for the static
+one-thread-per-particle kernel and for the mixed-precision kernel, and the
+CPU oracle is timed on the host cores.
+
+Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+METRIC = "particle cell-crossings/s at 1 GPU (FP64 vs mixed/batched); % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes: per crossing, the cell's six face flows + porosity (8 B each) + flags (4 B)
+# in FP64, six FP32 velocities + porosity + flags in mixed; per particle, the state read
+# (cell 4, xi/eta/zeta/t 32, status 4, ncross 4, hash 8 = 52 B), written back (52 B) and
+# the final global position (24 B)
+BYTES_PER_CROSSING = {"fp64": 60, "mixed": 32}
+BYTES_PER_PARTICLE = 52 + 52 + 24
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def workload(name):
+    from workloads import configs as C
+    if name == "C1":
+        return C.c1()
+    if name == "C2":
+        return C.c2()
+    if name == "C3":
+        return C.c3()
+    if name == "C4":
+        return C.c4()
+    if name == "C5":
+        return C.c5()
+    raise SystemExit("unknown workload " + name)
+
+
+DESCR = {
+    "C1": "C1: 40x40x1 homogeneous K=10 m/d, 1e3 particles, endpoint",
+    "C2": "C2: 100x100x10 lognormal K (sigma^2=1, corr. 5 cells), 1e6 particles, endpoint",
+    "C3": "C3: 200x200x20 lognormal K (sigma^2=4, corr. 8 cells), 2 wells + recharge, 1e7 particles",
+    "C4": "C4: 16 realisations 100x100x10 (sigma^2 ~ U[0.5,4]), 64 groups, 1.77e7 particles, batched",
+    "C5": "C5: 200x200x20 lognormal K (sigma^2=2), 1e6 particles, timeseries 100 snapshots [1e6,100,3]",
+}
+
+
+class Case:
+    """Device-resident inputs of one workload and the timed step."""
+
+    def __init__(self, w):
+        import torch
+        from paper_2302_13590_amd import pt
+        self.pt, self.torch, self.w = pt, torch, w
+        self.grids = [pt.pt_load_grid(g) for g in w.grids]
+        self.pristine = pt.DeviceParticles.from_numpy(w.particles, "cuda")
+        self.work = self.pristine.clone()
+        n = self.pristine.n
+        self.out_xyz = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+        self.snap = None
+        if w.snap_times is not None:
+            self.snap = torch.empty((n, len(w.snap_times), 3), dtype=torch.float64, device="cuda")
+        self.stream = torch.cuda.current_stream()
+
+    def opts(self, precision, schedule, **kw):
+        pt = self.pt
+        o = dict(precision=pt.PT_MIXED if precision == "mixed" else pt.PT_FP64,
+                 schedule=pt.PT_SCHED_STATIC if schedule == "static" else pt.PT_SCHED_PERSISTENT,
+                 layout=pt.PT_LAYOUT_CELL, use_graph=1, out_xyz=self.out_xyz, t_max=self.w.t_max)
+        if self.snap is not None:
+            o.update(mode=pt.PT_TIMESERIES, snap_times=self.w.snap_times, snap_xyz=self.snap)
+        o.update(kw)
+        return pt.make_opts(**o)
+
+    def step(self, o):
+        pt = self.pt
+        self.work.copy_(self.pristine)
+        run = pt.pt_track(self.grids, self.work, o, stream=self.stream,
+                          group_offsets=self.w.group_offsets, group_grid=self.w.group_grid)
+        s = pt.pt_results(run)
+        run.release()
+        return s
+
+    def time(self, o, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step(o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        summ = [self.step(o) for _ in range(steps)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        cross = summ[0]["crossings"]
+        assert all(s["crossings"] == cross for s in summ), "crossing count changed between steps"
+        kms = float(np.mean([s["kernel_ms"] for s in summ]))
+        return dict(wall_s=wall, ms_per_step=1e3 * wall / steps, crossings_per_step=cross,
+                    value=cross * steps / wall, kernel_ms=kms, summary=summ[0])
+
+    def release(self):
+        for g in self.grids:
+            g.release()
+
+
+def roofline(res, n, precision):
+    bytes_launch = res["crossings_per_step"] * BYTES_PER_CROSSING[precision] + n * BYTES_PER_PARTICLE
+    achieved = bytes_launch / (res["kernel_ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "bytes_per_launch": int(bytes_launch), "kernel_ms": round(res["kernel_ms"], 4),
+            "kernel": "k_track_persistent<%s, cell, endpoint>" % ("FP64" if precision == "fp64" else "mixed")}
+
+
+def cpu_baseline(w, n_threads):
+    """The oracle (plain FP64 CPU tracker) on the host cores, on a bounded sample."""
+    from oracle import oracle as O
+    p = w.particles
+    res = {}
+    # all host cores, dynamic scheduling of the particle loop (the paper's best protocol)
+    m = min(p.n, 1_000_000)
+    sub = p.subset(slice(0, m))
+    t0 = time.perf_counter()
+    r = O.track(w.grids[0], sub, t_max=w.t_max, threads=n_threads)
+    dt = time.perf_counter() - t0
+    res["all_cores"] = dict(value=float(r.ncross.astype(np.int64).sum()) / dt, seconds=dt, particles=m)
+    m1 = min(p.n, 50_000)
+    t0 = time.perf_counter()
+    r1 = O.track(w.grids[0], p.subset(slice(0, m1)), t_max=w.t_max, threads=1)
+    dt1 = time.perf_counter() - t0
+    res["one_core"] = dict(value=float(r1.ncross.astype(np.int64).sum()) / dt1, seconds=dt1, particles=m1)
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="C2", choices=sorted(DESCR))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--schedule", default="persistent", choices=["persistent", "static"])
+    ap.add_argument("--only", action="store_true",
+                    help="time only the primary variant (no other variants, no CPU baseline)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs the tracker on a single MI355X "
+              "(particles are independent; see DESIGN.md for how the path would shard).", file=sys.stderr)
+        return 2
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    from paper_2302_13590_amd import pt
+    pt.load_library()
+
+    log("building workload %s" % args.workload)
+    t0 = time.perf_counter()
+    w = workload(args.workload)
+    n = w.particles.n
+    log("inputs ready in %.1fs: %d particles, %d grid(s)" % (time.perf_counter() - t0, n, len(w.grids)))
+    case = Case(w)
+    primary = case.time(case.opts(args.precision, args.schedule), args.steps, args.warmup)
+    log("primary %s/%s: %.4g crossings/s, %.3f ms/step, kernel %.3f ms" % (
+        args.precision, args.schedule, primary["value"], primary["ms_per_step"], primary["kernel_ms"]))
+    variants = {}
+    if not args.only:
+        for prec, sched in (("fp64", "static"), ("fp64", "persistent"), ("mixed", "persistent")):
+            if (prec, sched) == (args.precision, args.schedule):
+                continue
+            r = case.time(case.opts(prec, sched), args.steps, args.warmup)
+            variants["%s_%s" % (prec, sched)] = dict(
+                value=r["value"], ms_per_step=round(r["ms_per_step"], 4),
+                kernel_ms=round(r["kernel_ms"], 4), crossings_per_step=r["crossings_per_step"],
+                roofline_frac=roofline(r, n, prec)["frac"])
+            log("variant %s/%s: %.4g crossings/s" % (prec, sched, r["value"]))
+    case.release()
+
+    out = {
+        "metric": METRIC,
+        "value": primary["value"],
+        "unit": "cell-crossings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(primary["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": DESCR[args.workload], "particles": n,
+                   "crossings_per_step": primary["crossings_per_step"], "precision": args.precision,
+                   "schedule": args.schedule, "layout": "cell", "launch": "hipGraph",
+                   "block": primary["summary"]["block"], "grid": primary["summary"]["grid"]},
+        "roofline": roofline(primary, n, args.precision),
+    }
+    if variants:
+        out["variants"] = variants
+    if not args.only and not args.no_cpu_baseline and len(w.grids) == 1:
+        cores = len(os.sched_getaffinity(0))
+        threads = min(cores, 16)
+        log("timing the CPU oracle on %d threads" % threads)
+        cb = cpu_baseline(w, threads)
+        out["cpu_baseline"] = {
+            "value": cb["all_cores"]["value"], "unit": "cell-crossings/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "first %d particles of the workload, OpenMP dynamic over particles, %.1f s; "
+                      "1 thread on the first %d particles: %.4g crossings/s; host %s"
+                      % (cb["all_cores"]["particles"], cb["all_cores"]["seconds"], cb["one_core"]["particles"],
+                         cb["one_core"]["value"], host_cpu_model()),
+        }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,218 @@
+/*
+ * pt.h -- C ABI of the MI355X (gfx950) particle tracker.
+ *
+ * Semi-analytical advective particle tracking through a steady, structured,
+ * cell-by-cell face-flow field.  The paper (Introduction; Methods, "MODPATH")
+ * describes the problem this library solves: a flow model provides the flow
+ * through every cell face; each particle is moved in a single step to the
+ * interface of its cell, handed to the neighbour across it, and this repeats
+ * until a stopping condition (a boundary face, the maximum tracking time, or
+ * a cell with sink flows); particles are independent of one another.  The
+ * simulation type and stop time come from the run configuration; outputs are
+ * indexed by particle (Methods, "MODPATH" and "Multiprocessing").
+ *
+ * Every call returns an int32 status: PT_OK (0) or a negative PT_ERR_* code.
+ * No exception crosses the ABI.  After a failing call, pt_last_error()
+ * returns a message for the calling thread.  Every argument is validated
+ * before any device work; a call that fails validation launches nothing.
+ * Device-side faults are reported by pt_results() of the run they belong to.
+ *
+ * Geometry and units.  Cells are indexed (i, j, k) with linear id
+ * c = (k*ny + j)*nx + i.  Face flows are positive in the +i / +j / +k
+ * direction, in volume per time (e.g. m^3/d).  Inside a cell a particle is
+ * located by local coordinates (xi, eta, zeta) in [0,1]^3 along i, j, k; its
+ * global position is x = x0 + (i + xi)*dx, y = y0 + (j + eta)*dy,
+ * z = z0 + (k + zeta)*dz.
+ *
+ * Per-cell motion (Pollock's semi-analytical step, to which the paper
+ * defers): each velocity component is interpolated linearly between the two
+ * face velocities u = Q / (n * (dx*dy*dz)) of its axis, u(xi) = u1 + A*xi with
+ * A = u2 - u1.  The components separate, so the particle reaches face xi_e
+ * (velocity u_e) after ln(u_e/u_p)/A (or (xi_e - xi)/u_p when A = 0), and
+ * xi(tau) = xi + u_p * (exp(A*tau) - 1)/A.  The earliest reachable face ends
+ * the step; exact ties go to the lowest axis (i, then j, then k).
+ */
+#ifndef PT_H
+#define PT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes --------------------------------------------------------------------- */
+#define PT_OK 0
+#define PT_ERR_INVALID_ARG (-1)  /* a pointer, size, enum or value is not acceptable            */
+#define PT_ERR_BAD_HANDLE (-2)   /* not a live handle of this library (e.g. released twice)     */
+#define PT_ERR_OOM (-3)          /* device or pinned host memory could not be allocated         */
+#define PT_ERR_NO_DEVICE (-4)    /* no usable HIP device                                        */
+#define PT_ERR_DEVICE (-5)       /* a HIP call or a kernel failed                               */
+#define PT_ERR_UNBALANCED (-6)   /* a cell's face flows do not balance within balance_tol       */
+#define PT_ERR_UNSUPPORTED (-7)  /* valid but not supported by this build (sizes, layouts)      */
+
+/* ---- particle statuses (int32, in/out) ------------------------------------------------ */
+#define PT_ACTIVE 0            /* to be tracked (a fresh release)                              */
+#define PT_BOUNDARY 1          /* left the domain through a boundary face                      */
+#define PT_SINK 2              /* entered (or was released in) a sink cell                     */
+#define PT_MAX_TIME 3          /* reached t_max; tracked again (resumed) by a later call       */
+#define PT_STEP_CAP 4          /* made max_steps crossings                                     */
+#define PT_STRANDED 5          /* no face of the current cell can be reached                   */
+#define PT_INVALID_START 6     /* bad cell, inactive cell, coordinate outside [0,1] or NaN t    */
+#define PT_INACTIVE_NEIGHBOR 7 /* the exit face leads into an inactive cell (bad flow field)   */
+#define PT_N_STATUS 8
+
+/* ---- cell flags ----------------------------------------------------------------------- */
+#define PT_CELL_ACTIVE 1       /* bit 0: the cell takes part in the flow model                 */
+#define PT_CELL_SINK 2         /* bit 1: the cell has sink flows (a well)                      */
+
+/* ---- enumerations --------------------------------------------------------------------- */
+#define PT_MEM_HOST 0
+#define PT_MEM_DEVICE 1
+
+#define PT_ENDPOINT 0          /* final state only                                             */
+#define PT_TIMESERIES 1        /* plus positions at the snapshot times                         */
+
+#define PT_FP64 0              /* all arithmetic in FP64                                       */
+#define PT_MIXED 1             /* in-cell arithmetic in FP32; time, global position and the    *
+                                * near-zero-gradient branch in FP64                            */
+
+#define PT_SCHED_AUTO 0
+#define PT_SCHED_STATIC 1      /* one thread per particle for its whole track                 */
+#define PT_SCHED_PERSISTENT 2  /* resident waves pull particles from a device work queue and   *
+                                * refill finished lanes (wave-level compaction)               */
+
+#define PT_LAYOUT_AUTO 0
+#define PT_LAYOUT_FACES 1      /* face-flow arrays + porosity + flags; velocities per step    */
+#define PT_LAYOUT_CELL 2       /* one packed record of six face velocities + flags per cell   */
+
+typedef struct pt_grid pt_grid; /* opaque: a flow field resident in device memory */
+typedef struct pt_run pt_run;   /* opaque: one enqueued tracking call            */
+
+/* ---- grid ----------------------------------------------------------------------------- */
+typedef struct {
+    int32_t nx, ny, nz;           /* cells along i, j, k; each >= 1, nx*ny*nz < 2^31            */
+    double dx, dy, dz;            /* cell sizes, finite and > 0                                  */
+    double x0, y0, z0;            /* global coordinates of the corner of cell (0,0,0)            */
+    const double* qx;             /* [nz][ny][nx+1] flow through the i faces, + = +i             */
+    const double* qy;             /* [nz][ny+1][nx] flow through the j faces, + = +j             */
+    const double* qz;             /* [nz+1][ny][nx] flow through the k faces, + = +k             */
+    const double* porosity;       /* [nz][ny][nx] in (0, inf), or NULL -> porosity_scalar        */
+    double porosity_scalar;       /* used when porosity == NULL; finite and > 0                  */
+    const int32_t* flags;         /* [nz][ny][nx] PT_CELL_* bits; NULL -> every cell active      */
+    int32_t mem;                  /* PT_MEM_HOST or PT_MEM_DEVICE for all the pointers above     */
+    double balance_tol;           /* < 0: no check.  Else every active non-sink cell must satisfy *
+                                   * |inflow - outflow| <= balance_tol * (sum of |face flows|),  *
+                                   * otherwise PT_ERR_UNBALANCED                                 */
+} pt_grid_desc;
+
+/*
+ * Copy a flow field to the device and build its device layouts (velocity
+ * records for FP64 and FP32, and the face arrays).  Validates the
+ * description first (sizes, finite flows, porosity > 0, known flag bits,
+ * optional balance).  The input arrays are read during the call only; the
+ * caller may free them on return.  `hip_stream` (a hipStream_t, NULL = the
+ * default stream) orders the copies; the call returns after they complete.
+ * On success *out owns the device copy until pt_release(*out).
+ */
+int pt_load_grid(const pt_grid_desc* desc, void* hip_stream, pt_grid** out);
+
+/* ---- particles -------------------------------------------------------------------------- */
+typedef struct {
+    int64_t n;                    /* number of particles, >= 0 (0 is a valid empty run)          */
+    int32_t* cell;                /* [n] linear cell id                      device, in/out      */
+    double* xi;                   /* [n] local coordinates in [0,1]          device, in/out      */
+    double* eta;
+    double* zeta;
+    double* t;                    /* [n] release time in, final time out     device, in/out      */
+    int32_t* status;              /* [n] PT_ACTIVE / PT_MAX_TIME are tracked, device, in/out     *
+                                   * any other status is left untouched                         */
+    int32_t* ncross;              /* [n] cell crossings so far               device, in/out      */
+    uint64_t* path_hash;          /* [n] FNV-1a style hash of the cells left device, in/out      *
+                                   * (start at 0xcbf29ce484222325 for a fresh particle): at each *
+                                   * crossing h = (h ^ (uint32)cell) * 0x100000001b3            */
+    int32_t n_groups;             /* 0: every particle uses grids[0].  Else particles            *
+                                   * [group_offsets[g], group_offsets[g+1]) use                  *
+                                   * grids[group_grid[g]]                                       */
+    const int64_t* group_offsets; /* host [n_groups+1], 0 = first <= ... <= last = n             */
+    const int32_t* group_grid;    /* host [n_groups], each in [0, n_grids)                       */
+} pt_particles;
+
+/* ---- options ---------------------------------------------------------------------------- */
+typedef struct {
+    int32_t mode;                 /* PT_ENDPOINT | PT_TIMESERIES                                 */
+    int32_t precision;            /* PT_FP64 | PT_MIXED                                          */
+    int32_t schedule;             /* PT_SCHED_*                                                  */
+    int32_t layout;               /* PT_LAYOUT_* (PT_MIXED requires CELL or AUTO)                */
+    int32_t direction;            /* +1 forward, -1 backward (all face flows negated)            */
+    int32_t stop_at_sink;         /* 1: stop on entering/release in a sink cell; 0: pass through */
+    double t_max;                 /* tracking time limit, not NaN (+inf allowed); a face reached *
+                                   * exactly at t_max is still crossed                          */
+    int64_t max_steps;            /* crossing cap per particle (counted over all calls), >= 1    */
+    const double* snap_times;     /* host [n_snap], non-decreasing, finite (PT_TIMESERIES)       */
+    int32_t n_snap;               /* >= 1 for PT_TIMESERIES                                      */
+    double* snap_xyz;             /* device [n][n_snap][3] global positions (PT_TIMESERIES):     *
+                                   * for a tracked particle, snapshot s gets its position if it  *
+                                   * was moving at s (release <= s, and s < termination time,    *
+                                   * or s <= t_max for MAX_TIME / STRANDED), NaN otherwise;      *
+                                   * a resumed (PT_MAX_TIME) particle keeps snapshots before its *
+                                   * current time                                               */
+    double* out_xyz;              /* device [n][3] final global position, or NULL; NaN for       *
+                                   * PT_INVALID_START                                           */
+    int32_t use_graph;            /* 1: launch through a cached hipGraph (replayed when the      *
+                                   * same arguments come again)                                 */
+    int32_t block;                /* threads per block, 0 = default; multiple of 64, <= 1024      */
+    int32_t blocks_per_cu;        /* persistent grid size per compute unit, 0 = default          */
+    int32_t refill;               /* persistent: refill a wave when at least this many lanes     *
+                                   * are idle, 1..64, 0 = default                               */
+    int32_t steps_per_refill;     /* persistent: crossings per lane between refill checks, 0 = d. */
+} pt_track_opts;
+
+/* Fill *o with the defaults: endpoint, FP64, auto schedule and layout, forward,
+ * stop at sinks, t_max = +inf, max_steps = 2^20, no snapshots. */
+void pt_default_opts(pt_track_opts* o);
+
+/*
+ * Enqueue tracking of every particle on `hip_stream` and return at once.
+ * grids[0 .. n_grids) are handles from pt_load_grid (n_grids >= 1).  All
+ * particle and output pointers are device memory owned by the caller, which
+ * must keep them alive and untouched until pt_results() of the returned run.
+ * On success *out is a run handle: pass it to pt_results() and then to
+ * pt_release().
+ */
+int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p,
+             const pt_track_opts* o, void* hip_stream, pt_run** out);
+
+typedef struct {
+    int64_t crossings;            /* cell crossings made in this call (all particles)            */
+    int64_t n_tracked;            /* particles with status ACTIVE or MAX_TIME at the start       */
+    int64_t status_count[PT_N_STATUS]; /* final status of the tracked particles                  */
+    double kernel_ms;             /* device time between the run's start and end events          */
+    int32_t schedule;             /* the schedule that ran (PT_SCHED_STATIC / _PERSISTENT)       */
+    int32_t layout;               /* the layout that ran                                         */
+    int32_t block, grid;          /* launch shape of the tracking kernel                         */
+    int64_t cr_ambiguous;         /* FP64 log1p/expm1/log evaluations whose correct rounding     *
+                                   * could not be decided (input within 2^-96 of a rounding      *
+                                   * boundary); the nearest double of a 2^-96-accurate value was *
+                                   * used.  Expected 0.                                          */
+} pt_summary;
+
+/* Wait for the run, then fill *out.  Reports asynchronous device errors of
+ * the run as PT_ERR_DEVICE.  May be called more than once. */
+int pt_results(pt_run* run, pt_summary* out);
+
+/* Release a pt_grid* or pt_run* (waits for a run still in flight).  NULL is a
+ * no-op.  A pointer that is not a live handle gives PT_ERR_BAD_HANDLE. */
+int pt_release(void* handle);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* pt_last_error(void);
+
+/* ABI version: 100 * major + minor. */
+int pt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PT_H */

@@ -29,7 +29,7 @@ def build(force: bool = True, src: str = _SRC, out: str = _LIB) -> str:
     """Compile the oracle with gcc (no FMA contraction, no fast math)."""
     if force or not os.path.exists(out):
         tmp = out + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc"] + CFLAGS + ["-o", tmp, src, "-lm"])
+        subprocess.check_call(["gcc"] + CFLAGS + ["-o", tmp, src, "-lquadmath", "-lm"])
         os.replace(tmp, out)
     return out
 
@@ -94,13 +94,17 @@ def _c(a, dtype):
 
 def track(grid, particles, *, direction: int = 1, t_max: float = math.inf,
           max_steps: int = 1 << 20, stop_at_sink: int = 1, snap_times=None, snap_init=None,
-          threads: int = 1, path_cap: int = 0, lib=None) -> Result:
+          threads: int = 0, path_cap: int = 0, lib=None) -> Result:
     """Track a copy of ``particles`` through ``grid``; returns the final state and outputs.
+
+    ``threads`` OpenMP threads over the particle loop (0: all available cores, at most 16).
 
     ``snap_init`` (optional [n, n_snap, 3]) is the snapshot buffer before the call,
     which matters only for resumed particles.
     """
     lib = lib or load()
+    if threads <= 0:
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
     g = grid
     qx, qy, qz = _c(g.qx, np.float64), _c(g.qy, np.float64), _c(g.qz, np.float64)
     flags = _c(g.flags, np.int32)

@@ -33,9 +33,10 @@
  *
  * Statuses: 0 ACTIVE, 1 BOUNDARY, 2 SINK, 3 MAX_TIME, 4 STEP_CAP, 5 STRANDED,
  * 6 INVALID_START, 7 INACTIVE_NEIGHBOR.
- * Build: gcc -O2 -fno-fast-math -ffp-contract=off (no FMA contraction).
+ * Build: gcc -O2 -fno-fast-math -ffp-contract=off (no FMA contraction), -lquadmath.
  */
 #include <math.h>
+#include <quadmath.h>
 #include <stdint.h>
 #include <stddef.h>
 
@@ -79,6 +80,17 @@ typedef struct {
     int32_t n_threads;
 } oracle_opts;
 
+/*
+ * Elementary functions, correctly rounded: evaluated in 113-bit quad precision and
+ * rounded once to double, i.e. the double nearest to the exact value (except for a
+ * quad value within 2^-112 of a rounding boundary).  The method's result is the exact
+ * solution of the cell ODE; the nearest double to each exact function value is the
+ * plainest FP64 reading of it, and it does not depend on a libm's last-bit choices.
+ */
+static double cr_log1p(double x) { return (double)log1pq((__float128)x); }
+static double cr_expm1(double x) { return (double)expm1q((__float128)x); }
+static double cr_log(double x) { return (double)logq((__float128)x); }
+
 /* One axis of the cell: face velocities u1 (low face) and u2 (high face). */
 typedef struct {
     double u1, u2;
@@ -90,7 +102,7 @@ static double advance(axis_vel v, double xi, double tau) {
     double up = v.u1 + A * xi;
     if (up == 0.0) return xi;
     double y = A * tau;
-    double psi = (y == 0.0) ? 1.0 : expm1(y) / y;
+    double psi = (y == 0.0) ? 1.0 : cr_expm1(y) / y;
     double xn = xi + (up * tau) * psi;
     if (xn < 0.0) xn = 0.0;
     if (xn > 1.0) xn = 1.0;
@@ -128,9 +140,9 @@ static double axis_exit_time(axis_vel v, double xi, double* xi_exit) {
     } else if (x < -0.5) {
         /* strongly decelerating: the ratio u_e/u_p is formed exactly enough,
          * 1 + x would lose digits */
-        dt = log(ue / up) / A;
+        dt = cr_log(ue / up) / A;
     } else {
-        dt = r * (log1p(x) / x);
+        dt = r * (cr_log1p(x) / x);
     }
     if (dt < 0.0) dt = 0.0;
     return dt;

@@ -1,0 +1,664 @@
+// Host side of libpt: argument validation, handles, device memory, launches.
+// Implements the C ABI declared in include/pt.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/pt.h"
+#include "pt_internal.h"
+
+using namespace pt;
+
+// ---------------------------------------------------------------------------------------------
+// errors
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_code(hipError_t e) {
+    switch (e) {
+        case hipErrorOutOfMemory: return PT_ERR_OOM;
+        case hipErrorNoDevice:
+        case hipErrorInvalidDevice:
+        case hipErrorInsufficientDriver: return PT_ERR_NO_DEVICE;
+        default: return PT_ERR_DEVICE;
+    }
+}
+
+#define HIP_TRY(call)                                                                             \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) {                                                                   \
+            (void)hipGetLastError();                                                              \
+            return fail(hip_code(e_), "%s failed: %s", #call, hipGetErrorString(e_));             \
+        }                                                                                         \
+    } while (0)
+
+// ---------------------------------------------------------------------------------------------
+// handles
+
+constexpr uint32_t kGridMagic = 0x50544744u;  // "PTGD"
+constexpr uint32_t kRunMagic = 0x5054524eu;   // "PTRN"
+
+std::mutex g_mu;
+std::unordered_set<void*> g_live;
+
+bool take_handle(void* h, uint32_t* magic_out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_live.find(h);
+    if (it == g_live.end()) return false;
+    *magic_out = *reinterpret_cast<uint32_t*>(h);
+    g_live.erase(it);
+    return true;
+}
+
+bool is_live(const void* h, uint32_t magic) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_live.count(const_cast<void*>(h)) && *reinterpret_cast<const uint32_t*>(h) == magic;
+}
+
+void add_live(void* h) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_live.insert(h);
+}
+
+int current_device(int* dev, int* n_cu) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return fail(PT_ERR_NO_DEVICE, "no HIP device available (%s)",
+                    e == hipSuccess ? "device count is 0" : hipGetErrorString(e));
+    }
+    HIP_TRY(hipGetDevice(dev));
+    if (n_cu) HIP_TRY(hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, *dev));
+    return PT_OK;
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+struct pt_grid {
+    uint32_t magic;
+    int device;
+    GridDev gd;
+    std::vector<void*> allocs;
+};
+
+struct pt_run {
+    uint32_t magic;
+    int device;
+    hipStream_t stream;
+    Counters* d_counters = nullptr;
+    Counters* h_counters = nullptr;     // pinned
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_done = nullptr;
+    bool launched = false;
+    int sched = 0, layout = 0, block = 0, grid = 0;
+    // per-run device tables (batched runs, snapshot times) and their pinned staging
+    void* d_tables = nullptr;
+    size_t d_tables_bytes = 0;
+    void* h_tables = nullptr;
+    size_t h_tables_bytes = 0;
+    // cached graph: [reset counters, track] for one exact set of kernel arguments
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<unsigned char> graph_key;
+};
+
+namespace {
+
+std::vector<pt_run*> g_pool;  // released runs kept for reuse (guarded by g_mu)
+
+void destroy_run(pt_run* r) {
+    if (r->exec) (void)hipGraphExecDestroy(r->exec);
+    if (r->graph) (void)hipGraphDestroy(r->graph);
+    if (r->ev0) (void)hipEventDestroy(r->ev0);
+    if (r->ev1) (void)hipEventDestroy(r->ev1);
+    if (r->ev_done) (void)hipEventDestroy(r->ev_done);
+    if (r->d_counters) (void)hipFree(r->d_counters);
+    if (r->h_counters) (void)hipHostFree(r->h_counters);
+    if (r->d_tables) (void)hipFree(r->d_tables);
+    if (r->h_tables) (void)hipHostFree(r->h_tables);
+    delete r;
+}
+
+int new_run(int device, pt_run** out) {
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (size_t q = 0; q < g_pool.size(); ++q) {
+            if (g_pool[q]->device == device) {
+                *out = g_pool[q];
+                g_pool.erase(g_pool.begin() + q);
+                (*out)->launched = false;
+                return PT_OK;
+            }
+        }
+    }
+    pt_run* r = new pt_run();
+    r->magic = kRunMagic;
+    r->device = device;
+    hipError_t e = hipMalloc(&r->d_counters, sizeof(Counters));
+    if (e == hipSuccess) e = hipHostMalloc(&r->h_counters, sizeof(Counters), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreate(&r->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&r->ev1);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev_done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        destroy_run(r);
+        return fail(hip_code(e), "run allocation failed: %s", hipGetErrorString(e));
+    }
+    *out = r;
+    return PT_OK;
+}
+
+int ensure_tables(pt_run* r, size_t bytes) {
+    if (bytes <= r->d_tables_bytes) return PT_OK;
+    if (r->d_tables) (void)hipFree(r->d_tables);
+    if (r->h_tables) (void)hipHostFree(r->h_tables);
+    r->d_tables = r->h_tables = nullptr;
+    r->d_tables_bytes = r->h_tables_bytes = 0;
+    if (r->exec) {
+        (void)hipGraphExecDestroy(r->exec);
+        (void)hipGraphDestroy(r->graph);
+        r->exec = nullptr;
+        r->graph = nullptr;
+        r->graph_key.clear();
+    }
+    HIP_TRY(hipMalloc(&r->d_tables, bytes));
+    HIP_TRY(hipHostMalloc(&r->h_tables, bytes, hipHostMallocDefault));
+    r->d_tables_bytes = r->h_tables_bytes = bytes;
+    return PT_OK;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------------------------
+// grid validation of host-resident inputs (device-resident inputs are checked by k_build)
+
+int check_host_grid(const pt_grid_desc* d) {
+    const int64_t nx = d->nx, ny = d->ny, nz = d->nz;
+    const int64_t nfx = (nx + 1) * ny * nz, nfy = nx * (ny + 1) * nz, nfz = nx * ny * (nz + 1);
+    const int64_t ncell = nx * ny * nz;
+    for (int64_t q = 0; q < nfx; ++q)
+        if (!is_fin(d->qx[q])) return fail(PT_ERR_INVALID_ARG, "qx[%lld] is not finite", (long long)q);
+    for (int64_t q = 0; q < nfy; ++q)
+        if (!is_fin(d->qy[q])) return fail(PT_ERR_INVALID_ARG, "qy[%lld] is not finite", (long long)q);
+    for (int64_t q = 0; q < nfz; ++q)
+        if (!is_fin(d->qz[q])) return fail(PT_ERR_INVALID_ARG, "qz[%lld] is not finite", (long long)q);
+    if (d->porosity)
+        for (int64_t c = 0; c < ncell; ++c)
+            if (!(d->porosity[c] > 0.0) || !is_fin(d->porosity[c]))
+                return fail(PT_ERR_INVALID_ARG, "porosity[%lld] must be finite and > 0", (long long)c);
+    if (d->flags)
+        for (int64_t c = 0; c < ncell; ++c)
+            if (d->flags[c] & ~(PT_CELL_ACTIVE | PT_CELL_SINK))
+                return fail(PT_ERR_INVALID_ARG, "flags[%lld] has unknown bits", (long long)c);
+    if (d->balance_tol >= 0.0) {
+        for (int64_t k = 0; k < nz; ++k)
+            for (int64_t j = 0; j < ny; ++j)
+                for (int64_t i = 0; i < nx; ++i) {
+                    const int64_t c = (k * ny + j) * nx + i;
+                    const int32_t f = d->flags ? d->flags[c] : PT_CELL_ACTIVE;
+                    if (!(f & PT_CELL_ACTIVE) || (f & PT_CELL_SINK)) continue;
+                    const int64_t fx = (k * ny + j) * (nx + 1) + i;
+                    const int64_t fy = (k * (ny + 1) + j) * nx + i;
+                    const int64_t fz = (k * ny + j) * nx + i;
+                    const double q[6] = {d->qx[fx], d->qx[fx + 1], d->qy[fy], d->qy[fy + nx],
+                                         d->qz[fz], d->qz[fz + nx * ny]};
+                    const double net = (q[0] - q[1]) + (q[2] - q[3]) + (q[4] - q[5]);
+                    double gross = 0.0;
+                    for (double v : q) gross += std::fabs(v);
+                    if (std::fabs(net) > d->balance_tol * gross)
+                        return fail(PT_ERR_UNBALANCED,
+                                    "cell (%lld,%lld,%lld): net flow %.3e exceeds %.3e of %.3e",
+                                    (long long)i, (long long)j, (long long)k, net, d->balance_tol, gross);
+                }
+    }
+    return PT_OK;
+}
+
+void free_grid(pt_grid* g) {
+    for (void* p : g->allocs) (void)hipFree(p);
+    delete g;
+}
+
+// Launch one kernel through the HIP module-less API.
+hipError_t launch(const void* fn, dim3 grid, dim3 block, void* arg, hipStream_t s) {
+    void* args[] = {arg};
+    return hipLaunchKernel(fn, grid, block, args, 0, s);
+}
+
+}  // namespace
+
+// =============================================================================================
+extern "C" {
+
+int pt_version(void) { return 100; }
+
+const char* pt_last_error(void) { return g_err.c_str(); }
+
+void pt_default_opts(pt_track_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->mode = PT_ENDPOINT;
+    o->precision = PT_FP64;
+    o->schedule = PT_SCHED_AUTO;
+    o->layout = PT_LAYOUT_AUTO;
+    o->direction = 1;
+    o->stop_at_sink = 1;
+    o->t_max = HUGE_VAL;
+    o->max_steps = 1 << 20;
+}
+
+int pt_load_grid(const pt_grid_desc* d, void* hip_stream, pt_grid** out) {
+    g_err.clear();
+    if (!d || !out) return fail(PT_ERR_INVALID_ARG, "desc and out must not be NULL");
+    *out = nullptr;
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1)
+        return fail(PT_ERR_INVALID_ARG, "nx, ny, nz must be >= 1 (got %d, %d, %d)", d->nx, d->ny, d->nz);
+    const int64_t ncell = (int64_t)d->nx * d->ny * d->nz;
+    if (ncell >= (int64_t(1) << 31) || (int64_t)(d->nx + 1) * d->ny * d->nz >= (int64_t(1) << 31))
+        return fail(PT_ERR_UNSUPPORTED, "grid too large: %lld cells (limit 2^31)", (long long)ncell);
+    if (!(d->dx > 0) || !(d->dy > 0) || !(d->dz > 0) || !is_fin(d->dx) || !is_fin(d->dy) || !is_fin(d->dz))
+        return fail(PT_ERR_INVALID_ARG, "dx, dy, dz must be finite and > 0");
+    if (!is_fin(d->x0) || !is_fin(d->y0) || !is_fin(d->z0))
+        return fail(PT_ERR_INVALID_ARG, "x0, y0, z0 must be finite");
+    if (!d->qx || !d->qy || !d->qz) return fail(PT_ERR_INVALID_ARG, "qx, qy, qz must not be NULL");
+    if (!d->porosity && (!(d->porosity_scalar > 0) || !is_fin(d->porosity_scalar)))
+        return fail(PT_ERR_INVALID_ARG, "porosity_scalar must be finite and > 0 when porosity is NULL");
+    if (d->mem != PT_MEM_HOST && d->mem != PT_MEM_DEVICE)
+        return fail(PT_ERR_INVALID_ARG, "mem must be PT_MEM_HOST or PT_MEM_DEVICE");
+    if (std::isnan(d->balance_tol)) return fail(PT_ERR_INVALID_ARG, "balance_tol is NaN");
+    if (d->mem == PT_MEM_HOST) {
+        int rc = check_host_grid(d);
+        if (rc != PT_OK) return rc;
+    }
+    int dev = 0;
+    int rc = current_device(&dev, nullptr);
+    if (rc != PT_OK) return rc;
+
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    const int64_t nx = d->nx, ny = d->ny, nz = d->nz;
+    const size_t bx = sizeof(double) * (nx + 1) * ny * nz, by = sizeof(double) * nx * (ny + 1) * nz,
+                 bz = sizeof(double) * nx * ny * (nz + 1), bc = sizeof(double) * ncell,
+                 bf = sizeof(int32_t) * ncell;
+    pt_grid* g = new pt_grid();
+    g->magic = kGridMagic;
+    g->device = dev;
+    auto alloc = [&](size_t bytes, void** p) -> hipError_t {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e == hipSuccess) g->allocs.push_back(*p);
+        return e;
+    };
+    void *qx, *qy, *qz, *por = nullptr, *flags, *r64, *r32, *err;
+    hipError_t e = alloc(bx, &qx);
+    if (e == hipSuccess) e = alloc(by, &qy);
+    if (e == hipSuccess) e = alloc(bz, &qz);
+    if (e == hipSuccess && d->porosity) e = alloc(bc, &por);
+    if (e == hipSuccess) e = alloc(bf, &flags);
+    if (e == hipSuccess) e = alloc(sizeof(CellRec64) * ncell, &r64);
+    if (e == hipSuccess) e = alloc(sizeof(CellRec32) * ncell, &r32);
+    if (e == hipSuccess) e = alloc(4 * sizeof(int), &err);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_grid(g);
+        return fail(hip_code(e), "grid allocation failed: %s", hipGetErrorString(e));
+    }
+    const hipMemcpyKind kind = d->mem == PT_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    e = hipMemcpyAsync(qx, d->qx, bx, kind, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(qy, d->qy, by, kind, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(qz, d->qz, bz, kind, s);
+    if (e == hipSuccess && d->porosity) e = hipMemcpyAsync(por, d->porosity, bc, kind, s);
+    if (e == hipSuccess && d->flags) e = hipMemcpyAsync(flags, d->flags, bf, kind, s);
+    if (e == hipSuccess) e = hipMemsetAsync(err, 0, 4 * sizeof(int), s);
+    if (e == hipSuccess && !d->flags) {
+        std::vector<int32_t> ones(ncell, PT_CELL_ACTIVE);
+        e = hipMemcpyAsync(flags, ones.data(), bf, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    GridDev& gd = g->gd;
+    gd.rec64 = static_cast<CellRec64*>(r64);
+    gd.rec32 = static_cast<CellRec32*>(r32);
+    gd.qx = static_cast<double*>(qx);
+    gd.qy = static_cast<double*>(qy);
+    gd.qz = static_cast<double*>(qz);
+    gd.por = static_cast<double*>(por);
+    gd.flags = static_cast<int32_t*>(flags);
+    gd.por_scalar = d->porosity ? 0.0 : d->porosity_scalar;
+    gd.dx = d->dx; gd.dy = d->dy; gd.dz = d->dz;
+    gd.x0 = d->x0; gd.y0 = d->y0; gd.z0 = d->z0;
+    gd.V = (d->dx * d->dy) * d->dz;
+    gd.nx = d->nx; gd.ny = d->ny; gd.nz = d->nz; gd.pad = 0;
+    BuildParams B;
+    B.g = gd;
+    B.rec64 = static_cast<CellRec64*>(r64);
+    B.rec32 = static_cast<CellRec32*>(r32);
+    B.balance_tol = d->balance_tol;
+    B.err = static_cast<int*>(err);
+    if (e == hipSuccess)
+        e = launch(build_kernel(), dim3((unsigned)((ncell + 255) / 256)), dim3(256), &B, s);
+    int herr[4] = {0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(herr, err, sizeof herr, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_grid(g);
+        return fail(hip_code(e), "grid upload failed: %s", hipGetErrorString(e));
+    }
+    if (herr[0] || herr[1] || herr[2] || herr[3]) {
+        free_grid(g);
+        if (herr[0]) return fail(PT_ERR_INVALID_ARG, "a face flow is not finite");
+        if (herr[1]) return fail(PT_ERR_INVALID_ARG, "a porosity is not finite and > 0");
+        if (herr[2]) return fail(PT_ERR_INVALID_ARG, "a cell flag has unknown bits");
+        return fail(PT_ERR_UNBALANCED, "a cell's face flows do not balance within balance_tol");
+    }
+    add_live(g);
+    *out = g;
+    return PT_OK;
+}
+
+int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p, const pt_track_opts* o,
+             void* hip_stream, pt_run** out) {
+    g_err.clear();
+    if (!out) return fail(PT_ERR_INVALID_ARG, "out must not be NULL");
+    *out = nullptr;
+    if (!grids || n_grids < 1) return fail(PT_ERR_INVALID_ARG, "need at least one grid");
+    if (n_grids > 4096) return fail(PT_ERR_UNSUPPORTED, "at most 4096 grids per call");
+    for (int32_t q = 0; q < n_grids; ++q)
+        if (!grids[q] || !is_live(grids[q], kGridMagic))
+            return fail(PT_ERR_BAD_HANDLE, "grids[%d] is not a live grid handle", q);
+    if (!p || !o) return fail(PT_ERR_INVALID_ARG, "particles and options must not be NULL");
+    if (p->n < 0) return fail(PT_ERR_INVALID_ARG, "n must be >= 0");
+    if (p->n > 0 && (!p->cell || !p->xi || !p->eta || !p->zeta || !p->t || !p->status || !p->ncross ||
+                     !p->path_hash))
+        return fail(PT_ERR_INVALID_ARG, "a particle state array is NULL");
+    if (o->mode != PT_ENDPOINT && o->mode != PT_TIMESERIES) return fail(PT_ERR_INVALID_ARG, "bad mode");
+    if (o->precision != PT_FP64 && o->precision != PT_MIXED) return fail(PT_ERR_INVALID_ARG, "bad precision");
+    if (o->schedule < PT_SCHED_AUTO || o->schedule > PT_SCHED_PERSISTENT)
+        return fail(PT_ERR_INVALID_ARG, "bad schedule");
+    if (o->layout < PT_LAYOUT_AUTO || o->layout > PT_LAYOUT_CELL) return fail(PT_ERR_INVALID_ARG, "bad layout");
+    if (o->direction != 1 && o->direction != -1) return fail(PT_ERR_INVALID_ARG, "direction must be +1 or -1");
+    if (o->stop_at_sink != 0 && o->stop_at_sink != 1) return fail(PT_ERR_INVALID_ARG, "stop_at_sink must be 0 or 1");
+    if (std::isnan(o->t_max)) return fail(PT_ERR_INVALID_ARG, "t_max is NaN");
+    if (o->max_steps < 1 || o->max_steps > INT32_MAX)
+        return fail(PT_ERR_INVALID_ARG, "max_steps must be in [1, 2^31-1]");
+    if (o->block != 0 && (o->block < 64 || o->block > 1024 || o->block % 64))
+        return fail(PT_ERR_INVALID_ARG, "block must be 0 or a multiple of 64 in [64, 1024]");
+    if (o->block > 256) return fail(PT_ERR_UNSUPPORTED, "block > 256 exceeds the kernels' launch bounds");
+    if (o->refill < 0 || o->refill > 64) return fail(PT_ERR_INVALID_ARG, "refill must be in [0, 64]");
+    if (o->steps_per_refill < 0 || o->blocks_per_cu < 0)
+        return fail(PT_ERR_INVALID_ARG, "steps_per_refill and blocks_per_cu must be >= 0");
+    if (o->precision == PT_MIXED && o->layout == PT_LAYOUT_FACES)
+        return fail(PT_ERR_UNSUPPORTED, "mixed precision needs the packed cell layout");
+    const bool ts = o->mode == PT_TIMESERIES;
+    if (ts) {
+        if (o->n_snap < 1 || !o->snap_times || !o->snap_xyz)
+            return fail(PT_ERR_INVALID_ARG, "timeseries needs snap_times, n_snap >= 1 and snap_xyz");
+        for (int32_t q = 0; q < o->n_snap; ++q) {
+            if (!is_fin(o->snap_times[q])) return fail(PT_ERR_INVALID_ARG, "snap_times[%d] is not finite", q);
+            if (q && o->snap_times[q] < o->snap_times[q - 1])
+                return fail(PT_ERR_INVALID_ARG, "snap_times must be non-decreasing");
+        }
+    }
+    const int32_t n_groups = p->n_groups;
+    if (n_groups < 0) return fail(PT_ERR_INVALID_ARG, "n_groups must be >= 0");
+    if (n_grids > 1 && n_groups == 0) return fail(PT_ERR_INVALID_ARG, "several grids need particle groups");
+    if (n_groups > 0) {
+        if (!p->group_offsets || !p->group_grid)
+            return fail(PT_ERR_INVALID_ARG, "group_offsets and group_grid must not be NULL");
+        if (p->group_offsets[0] != 0 || p->group_offsets[n_groups] != p->n)
+            return fail(PT_ERR_INVALID_ARG, "group_offsets must start at 0 and end at n");
+        for (int32_t q = 0; q < n_groups; ++q) {
+            if (p->group_offsets[q + 1] < p->group_offsets[q])
+                return fail(PT_ERR_INVALID_ARG, "group_offsets must be non-decreasing");
+            if (p->group_grid[q] < 0 || p->group_grid[q] >= n_grids)
+                return fail(PT_ERR_INVALID_ARG, "group_grid[%d] out of range", q);
+        }
+    }
+    int dev = 0, n_cu = 0;
+    int rc = current_device(&dev, &n_cu);
+    if (rc != PT_OK) return rc;
+    for (int32_t q = 0; q < n_grids; ++q)
+        if (grids[q]->device != dev)
+            return fail(PT_ERR_INVALID_ARG, "grids[%d] lives on device %d, current is %d", q, grids[q]->device, dev);
+
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    pt_run* r = nullptr;
+    rc = new_run(dev, &r);
+    if (rc != PT_OK) return rc;
+    r->stream = s;
+
+    // kernel choice and launch shape
+    const bool batched = n_groups > 0;
+    KernelKey key;
+    key.precision = o->precision == PT_MIXED ? PMIX : P64;
+    key.layout = o->layout == PT_LAYOUT_FACES ? L_FACES : L_CELL;
+    key.timeseries = ts ? 1 : 0;
+    key.batched = batched ? 1 : 0;
+    key.sched = o->schedule == PT_SCHED_STATIC ? S_STATIC : S_PERSISTENT;
+    const void* fn = track_kernel(key);
+    const int block = o->block ? o->block : 256;
+    int grid;
+    if (key.sched == S_STATIC) {
+        grid = (int)std::max<int64_t>(1, (p->n + block - 1) / block);
+    } else {
+        int per_cu = o->blocks_per_cu;
+        if (!per_cu) {
+            int occ = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, block, 0) != hipSuccess || occ < 1) {
+                (void)hipGetLastError();
+                occ = 2;
+            }
+            per_cu = occ;
+        }
+        grid = std::max(1, n_cu * per_cu);
+        const int64_t need = (p->n + block - 1) / block;
+        if (need < grid) grid = (int)std::max<int64_t>(1, need);
+    }
+    r->sched = key.sched == S_STATIC ? PT_SCHED_STATIC : PT_SCHED_PERSISTENT;
+    r->layout = key.layout == L_FACES ? PT_LAYOUT_FACES : PT_LAYOUT_CELL;
+    r->block = block;
+    r->grid = grid;
+
+    // per-run tables: grid views, group table, snapshot times
+    const size_t b_grids = batched ? align_up(sizeof(GridDev) * n_grids, 256) : 0;
+    const size_t b_offs = batched ? align_up(sizeof(int64_t) * (n_groups + 1), 256) : 0;
+    const size_t b_gg = batched ? align_up(sizeof(int32_t) * n_groups, 256) : 0;
+    const size_t b_snap = ts ? align_up(sizeof(double) * o->n_snap, 256) : 0;
+    const size_t total = b_grids + b_offs + b_gg + b_snap;
+    TrackParams P;
+    std::memset(&P, 0, sizeof P);
+    if (total) {
+        rc = ensure_tables(r, total);
+        if (rc != PT_OK) {
+            destroy_run(r);
+            return rc;
+        }
+        // the previous use of this pinned buffer has completed: runs are reused only after
+        // pt_release, which waits for them
+        unsigned char* h = static_cast<unsigned char*>(r->h_tables);
+        unsigned char* dd = static_cast<unsigned char*>(r->d_tables);
+        size_t off = 0;
+        if (batched) {
+            GridDev* hg = reinterpret_cast<GridDev*>(h + off);
+            for (int32_t q = 0; q < n_grids; ++q) hg[q] = grids[q]->gd;
+            P.grids = reinterpret_cast<const GridDev*>(dd + off);
+            off += b_grids;
+            std::memcpy(h + off, p->group_offsets, sizeof(int64_t) * (n_groups + 1));
+            P.group_offsets = reinterpret_cast<const int64_t*>(dd + off);
+            off += b_offs;
+            std::memcpy(h + off, p->group_grid, sizeof(int32_t) * n_groups);
+            P.group_grid = reinterpret_cast<const int32_t*>(dd + off);
+            off += b_gg;
+        }
+        if (ts) {
+            std::memcpy(h + off, o->snap_times, sizeof(double) * o->n_snap);
+            P.snap_times = reinterpret_cast<const double*>(dd + off);
+            off += b_snap;
+        }
+        hipError_t e = hipMemcpyAsync(r->d_tables, r->h_tables, total, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            destroy_run(r);
+            return fail(hip_code(e), "table upload failed: %s", hipGetErrorString(e));
+        }
+    }
+    P.n = p->n;
+    P.cell = p->cell;
+    P.xi = p->xi;
+    P.eta = p->eta;
+    P.zeta = p->zeta;
+    P.t = p->t;
+    P.status = p->status;
+    P.ncross = p->ncross;
+    P.hash = p->path_hash;
+    P.n_groups = n_groups;
+    P.n_grids = n_grids;
+    P.g0 = grids[0]->gd;
+    P.t_max = o->t_max;
+    P.max_steps = o->max_steps;
+    P.sign = o->direction < 0 ? -1.0 : 1.0;
+    P.stop_at_sink = o->stop_at_sink;
+    P.n_snap = ts ? o->n_snap : 0;
+    P.snap_xyz = ts ? o->snap_xyz : nullptr;
+    P.out_xyz = o->out_xyz;
+    P.counters = r->d_counters;
+    P.refill = o->refill ? o->refill : 32;
+    P.steps_per_refill = o->steps_per_refill ? o->steps_per_refill : 1;
+
+    hipError_t e = hipEventRecord(r->ev0, s);
+    if (e == hipSuccess) {
+        if (o->use_graph) {
+            std::vector<unsigned char> gkey(sizeof P + sizeof(const void*) + 2 * sizeof(int));
+            unsigned char* kp = gkey.data();
+            std::memcpy(kp, &P, sizeof P);
+            std::memcpy(kp + sizeof P, &fn, sizeof fn);
+            std::memcpy(kp + sizeof P + sizeof fn, &grid, sizeof grid);
+            std::memcpy(kp + sizeof P + sizeof fn + sizeof grid, &block, sizeof block);
+            if (!r->exec || r->graph_key != gkey) {
+                if (r->exec) {
+                    (void)hipGraphExecDestroy(r->exec);
+                    (void)hipGraphDestroy(r->graph);
+                    r->exec = nullptr;
+                    r->graph = nullptr;
+                }
+                hipGraph_t gr = nullptr;
+                hipGraphNode_t n_reset = nullptr, n_track = nullptr;
+                Counters* cptr = r->d_counters;
+                void* reset_args[] = {&cptr};
+                void* track_args[] = {&P};
+                hipKernelNodeParams kr;
+                std::memset(&kr, 0, sizeof kr);
+                kr.func = const_cast<void*>(reset_kernel());
+                kr.gridDim = dim3(1);
+                kr.blockDim = dim3(64);
+                kr.kernelParams = reset_args;
+                hipKernelNodeParams kt;
+                std::memset(&kt, 0, sizeof kt);
+                kt.func = const_cast<void*>(fn);
+                kt.gridDim = dim3(grid);
+                kt.blockDim = dim3(block);
+                kt.kernelParams = track_args;
+                e = hipGraphCreate(&gr, 0);
+                if (e == hipSuccess) e = hipGraphAddKernelNode(&n_reset, gr, nullptr, 0, &kr);
+                if (e == hipSuccess && p->n > 0) e = hipGraphAddKernelNode(&n_track, gr, &n_reset, 1, &kt);
+                if (e == hipSuccess) e = hipGraphInstantiate(&r->exec, gr, nullptr, nullptr, 0);
+                if (e == hipSuccess) {
+                    r->graph = gr;
+                    r->graph_key = gkey;
+                } else if (gr) {
+                    (void)hipGraphDestroy(gr);
+                    r->exec = nullptr;
+                }
+            }
+            if (e == hipSuccess) e = hipGraphLaunch(r->exec, s);
+        } else {
+            Counters* cptr = r->d_counters;
+            e = launch(reset_kernel(), dim3(1), dim3(64), &cptr, s);
+            if (e == hipSuccess && p->n > 0) e = launch(fn, dim3(grid), dim3(block), &P, s);
+        }
+    }
+    if (e == hipSuccess) e = hipEventRecord(r->ev1, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->h_counters, r->d_counters, sizeof(Counters), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(r->ev_done, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(s);
+        destroy_run(r);
+        return fail(hip_code(e), "launch failed: %s", hipGetErrorString(e));
+    }
+    r->launched = true;
+    add_live(r);
+    *out = r;
+    return PT_OK;
+}
+
+int pt_results(pt_run* r, pt_summary* out) {
+    g_err.clear();
+    if (!r || !is_live(r, kRunMagic)) return fail(PT_ERR_BAD_HANDLE, "not a live run handle");
+    if (!out) return fail(PT_ERR_INVALID_ARG, "out must not be NULL");
+    HIP_TRY(hipEventSynchronize(r->ev_done));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, r->ev0, r->ev1));
+    std::memset(out, 0, sizeof *out);
+    const Counters& c = *r->h_counters;
+    out->crossings = (int64_t)c.crossings;
+    int64_t tracked = 0;
+    for (int q = 0; q < PT_N_STATUS; ++q) {
+        out->status_count[q] = (int64_t)c.status[q];
+        tracked += (int64_t)c.status[q];
+    }
+    out->n_tracked = tracked;
+    out->kernel_ms = ms;
+    out->schedule = r->sched;
+    out->layout = r->layout;
+    out->block = r->block;
+    out->grid = r->grid;
+    out->cr_ambiguous = (int64_t)c.cr_ambiguous;
+    return PT_OK;
+}
+
+int pt_release(void* h) {
+    g_err.clear();
+    if (!h) return PT_OK;
+    uint32_t magic = 0;
+    if (!take_handle(h, &magic)) return fail(PT_ERR_BAD_HANDLE, "not a live handle (released twice?)");
+    if (magic == kGridMagic) {
+        pt_grid* g = static_cast<pt_grid*>(h);
+        (void)hipDeviceSynchronize();  // no run may still read it
+        free_grid(g);
+        return PT_OK;
+    }
+    pt_run* r = static_cast<pt_run*>(h);
+    hipError_t e = hipEventSynchronize(r->ev_done);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        destroy_run(r);
+        return fail(hip_code(e), "run failed on the device: %s", hipGetErrorString(e));
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_pool.size() < 8) g_pool.push_back(r);
+    else destroy_run(r);
+    return PT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,277 @@
+// Correctly rounded FP64 log1p, expm1 and log for the FP64 tracking path.
+//
+// Each function returns the double nearest to the exact function value.  A
+// quick phase evaluates the function as a double-double with a relative error
+// below 2^-68 and applies a rounding test (Ziv's strategy): if every real number
+// within that error of the double-double rounds to the same double, that double
+// is the correctly rounded result.  Otherwise an accurate phase (error below
+// 2^-96) is evaluated and tested again; if that test fails too (an input closer
+// to a rounding boundary than 2^-96 relative), the nearest double of the
+// accurate value is returned and `ambiguous` is raised.
+//
+// Reductions:
+//   log(y),  y = 2^k m, m in [sqrt(1/2), sqrt(2)]:  c = RN(256/j), j = round(256 m),
+//            r = m c - 1 (|r| < 2^-8.4, formed exactly with FMA products),
+//            log y = k ln2 - ln c + log1p(r), log1p(r) by its Taylor series.
+//   log1p(x) = log(y) with y = 1 + x carried exactly as a double-double.
+//   expm1(x), x = (128 k + j) ln2/128 + r (|r| <= ln2/256):
+//            expm1 x = (2^k 2^(j/128) - 1) + 2^k 2^(j/128) (e^r - 1),
+//            e^r - 1 by its Taylor series.
+// Constants come from pt_crtables.h (double-double, generated in decimal).
+//
+// Written for both the device (HIP) and a host build used by the CPU tests.
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+
+#ifdef __HIPCC__
+#include <hip/hip_runtime.h>
+#define PT_CR_HD __host__ __device__ inline
+#define PT_CR_TABLE static constexpr
+#else
+#define PT_CR_HD static inline
+#define PT_CR_TABLE static constexpr
+#endif
+
+#include "pt_crtables.h"
+
+namespace ptcr {
+
+struct dd {
+    double h, l;
+};
+
+PT_CR_HD dd two_sum(double a, double b) {
+    const double s = a + b;
+    const double bb = s - a;
+    const double e = (a - (s - bb)) + (b - bb);
+    return {s, e};
+}
+
+// requires |a| >= |b| or a == 0
+PT_CR_HD dd fast_two_sum(double a, double b) {
+    const double s = a + b;
+    const double e = b - (s - a);
+    return {s, e};
+}
+
+PT_CR_HD dd two_prod(double a, double b) {
+    const double p = a * b;
+    return {p, fma(a, b, -p)};
+}
+
+PT_CR_HD dd dd_add(dd x, dd y) {
+    const dd s = two_sum(x.h, y.h);
+    const dd t = two_sum(x.l, y.l);
+    const dd v = fast_two_sum(s.h, s.l + t.h);
+    return fast_two_sum(v.h, t.l + v.l);
+}
+
+PT_CR_HD dd dd_add_d(dd x, double d) {
+    const dd s = two_sum(x.h, d);
+    return fast_two_sum(s.h, s.l + x.l);
+}
+
+PT_CR_HD dd dd_mul(dd x, dd y) {
+    dd p = two_prod(x.h, y.h);
+    p.l += fma(x.h, y.l, x.l * y.h);
+    return fast_two_sum(p.h, p.l);
+}
+
+PT_CR_HD dd dd_mul_d(dd x, double d) {
+    dd p = two_prod(x.h, d);
+    p.l = fma(x.l, d, p.l);
+    return fast_two_sum(p.h, p.l);
+}
+
+// If every real within eps*|v| of v.h + v.l rounds to the same double, store it and
+// return true.
+PT_CR_HD bool round_test(dd v, double eps, double* out) {
+    const double e = eps * fabs(v.h);
+    const double a = v.h + (v.l - e);
+    const double b = v.h + (v.l + e);
+    if (a == b) {
+        *out = a;
+        return true;
+    }
+    return false;
+}
+
+constexpr double kEpsQuick = 0x1p-68;
+constexpr double kEpsAccurate = 0x1p-96;
+
+// ----------------------------------------------------------------------------------- log
+
+struct LogRed {
+    int k;
+    int j;
+    dd r;
+};
+
+// y = yh + yl > 0 (yh normal or subnormal, |yl| <= ulp(yh)).
+PT_CR_HD LogRed log_reduce(double yh, double yl) {
+    int e;
+    double m = frexp(yh, &e);   // m in [1/2, 1)
+    m *= 2.0;
+    e -= 1;                     // m in [1, 2)
+    if (m > PT_CR_SQRT2) {
+        m *= 0.5;
+        e += 1;
+    }
+    const double ml = ldexp(yl, -e);
+    const int j = (int)rint(m * 256.0);
+    const double c = PT_CR_LOG_C[j - PT_CR_LOG_J0];
+    const dd p = two_prod(m, c);              // exact
+    dd r = fast_two_sum(p.h - 1.0, p.l);      // p.h - 1 is exact
+    r = dd_add(r, two_prod(ml, c));
+    return {e, j, r};
+}
+
+PT_CR_HD dd log_sum(const LogRed& R, dd p) {
+    const double kd = (double)R.k;
+    dd kl = two_prod(kd, PT_CR_LN2_H);
+    kl.l = fma(kd, PT_CR_LN2_L, kl.l);
+    const dd L = {PT_CR_LOG_L[R.j - PT_CR_LOG_J0][0], PT_CR_LOG_L[R.j - PT_CR_LOG_J0][1]};
+    return dd_add(kl, dd_add(L, p));
+}
+
+// log1p(r) for |r| < 2^-8.4 with relative error < 2^-70.
+PT_CR_HD dd log1p_series_quick(dd r) {
+    const double x = r.h;
+    double T = -0x1.999999999999ap-4;                 // -1/10
+    T = fma(x, T, 0x1.c71c71c71c71cp-4);              //  1/9
+    T = fma(x, T, -0x1.0000000000000p-3);             // -1/8
+    T = fma(x, T, 0x1.2492492492492p-3);              //  1/7
+    T = fma(x, T, -0x1.5555555555555p-3);             // -1/6
+    T = fma(x, T, 0x1.999999999999ap-3);              //  1/5
+    T = fma(x, T, -0x1.0000000000000p-2);             // -1/4
+    T = fma(x, T, 0x1.5555555555555p-2);              //  1/3
+    dd S = two_prod(x, T);
+    S.l = fma(r.l, T, S.l);
+    S = dd_add_d(S, -0.5);                            // -1/2 + r T
+    const dd r2 = dd_mul(r, r);
+    return dd_add(r, dd_mul(r2, S));
+}
+
+// log1p(r) for |r| < 2^-8.4 with relative error < 2^-100.
+PT_CR_HD dd log1p_series_accurate(dd r) {
+    // log1p(r) = r * sum_{k>=1} (-1)^(k+1) r^(k-1) / k, Horner from k = 14
+    dd S = {PT_CR_INVK[14][0], PT_CR_INVK[14][1]};
+    S.h = -S.h;
+    S.l = -S.l;
+    for (int k = 13; k >= 1; --k) {
+        dd c = {PT_CR_INVK[k][0], PT_CR_INVK[k][1]};
+        if (!(k & 1)) {
+            c.h = -c.h;
+            c.l = -c.l;
+        }
+        S = dd_add(c, dd_mul(r, S));
+    }
+    return dd_mul(r, S);
+}
+
+PT_CR_HD double log_dd_cr(double yh, double yl, unsigned* ambiguous) {
+    const LogRed R = log_reduce(yh, yl);
+    double out;
+    const dd q = log_sum(R, log1p_series_quick(R.r));
+    if (round_test(q, kEpsQuick, &out)) return out;
+    const dd a = log_sum(R, log1p_series_accurate(R.r));
+    if (round_test(a, kEpsAccurate, &out)) return out;
+    *ambiguous += 1u;
+    return a.h + a.l;
+}
+
+// Correctly rounded log1p(x).
+PT_CR_HD double log1p_cr(double x, unsigned* ambiguous) {
+    if (!(x > -1.0)) {
+        if (x == -1.0) return -__builtin_huge_val();
+        return __builtin_nan("");       // x < -1 or NaN
+    }
+    if (fabs(x) < 0x1p-60) return x;    // log1p(x) = x (1 - x/2 + ...) rounds to x
+    if (x == __builtin_huge_val()) return x;
+    const dd y = two_sum(1.0, x);       // 1 + x exactly
+    return log_dd_cr(y.h, y.l, ambiguous);
+}
+
+// Correctly rounded log(x).
+PT_CR_HD double log_cr(double x, unsigned* ambiguous) {
+    if (!(x > 0.0)) {
+        if (x == 0.0) return -__builtin_huge_val();
+        return __builtin_nan("");
+    }
+    if (x == __builtin_huge_val()) return x;
+    if (x == 1.0) return 0.0;
+    return log_dd_cr(x, 0.0, ambiguous);
+}
+
+// ----------------------------------------------------------------------------------- expm1
+
+struct ExpRed {
+    int k;
+    int j;
+    dd r;
+};
+
+PT_CR_HD ExpRed exp_reduce(double x) {
+    const double Kd = rint(x * PT_CR_INV_LN2_128);
+    const int K = (int)Kd;
+    const double r0 = x - Kd * PT_CR_LN2_128_1;   // exact
+    dd m = two_prod(Kd, PT_CR_LN2_128_2);
+    m.l = fma(Kd, PT_CR_LN2_128_3, m.l);
+    const dd r = dd_add({r0, 0.0}, {-m.h, -m.l});
+    return {K >> 7, K & 127, r};
+}
+
+// e^r - 1 for |r| <= ln2/256 with relative error < 2^-70.
+PT_CR_HD dd expm1_series_quick(dd r) {
+    const double x = r.h;
+    double U = 0x1.a01a01a01a01ap-16;              // 1/8!
+    U = fma(x, U, 0x1.a01a01a01a01ap-13);          // 1/7!
+    U = fma(x, U, 0x1.6c16c16c16c17p-10);          // 1/6!
+    U = fma(x, U, 0x1.1111111111111p-7);           // 1/5!
+    U = fma(x, U, 0x1.5555555555555p-5);           // 1/4!
+    U = fma(x, U, 0x1.5555555555555p-3);           // 1/3!
+    dd S = two_prod(x, U);
+    S.l = fma(r.l, U, S.l);
+    S = dd_add_d(S, 0.5);                          // 1/2 + r U
+    const dd r2 = dd_mul(r, r);
+    return dd_add(r, dd_mul(r2, S));
+}
+
+// e^r - 1 for |r| <= ln2/256 with relative error < 2^-100.
+PT_CR_HD dd expm1_series_accurate(dd r) {
+    dd S = {PT_CR_INVF[15][0], PT_CR_INVF[15][1]};
+    for (int k = 14; k >= 1; --k) S = dd_add({PT_CR_INVF[k][0], PT_CR_INVF[k][1]}, dd_mul(r, S));
+    return dd_mul(r, S);
+}
+
+// (2^k T_j - 1) + 2^k T_j q, scaled by 2^-s (s > 0 only near overflow).
+PT_CR_HD dd expm1_combine(const ExpRed& R, dd q, int s) {
+    if (R.k == 0 && R.j == 0) return q;
+    const int k = R.k - s;
+    const dd T = {ldexp(PT_CR_EXP_T[R.j][0], k), ldexp(PT_CR_EXP_T[R.j][1], k)};
+    const double one = ldexp(1.0, -s);
+    const dd A = dd_add_d(T, -one);
+    return dd_add(A, dd_mul(T, q));
+}
+
+// Correctly rounded expm1(x).
+PT_CR_HD double expm1_cr(double x, unsigned* ambiguous) {
+    if (!(x == x)) return x;
+    if (fabs(x) < 0x1p-60) return x;     // expm1(x) = x (1 + x/2 + ...) rounds to x
+    if (x > 710.0) return __builtin_huge_val();
+    if (x < -40.0) return -1.0;          // e^x < 2^-57: -1 + e^x rounds to -1
+    const ExpRed R = exp_reduce(x);
+    const int s = (R.k > 1000) ? 2 : 0;  // keep 2^k finite; the final scaling by 4 is exact
+    const double back = s ? 4.0 : 1.0;
+    double out;
+    const dd q = expm1_combine(R, expm1_series_quick(R.r), s);
+    if (round_test(q, kEpsQuick, &out)) return out * back;
+    const dd a = expm1_combine(R, expm1_series_accurate(R.r), s);
+    if (round_test(a, kEpsAccurate, &out)) return out * back;
+    *ambiguous += 1u;
+    return (a.h + a.l) * back;
+}
+
+}  // namespace ptcr

@@ -1,0 +1,121 @@
+// Internal declarations shared by the kernels and the host side of libpt.
+// Device layouts of the flow field and of the tracking-kernel parameters.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pt {
+
+// Per-cell flag word of the packed layouts.  Bits 0-1 are the cell's own
+// PT_CELL_* flags; for each face f (0 = -i, 1 = +i, 2 = -j, 3 = +j, 4 = -k,
+// 5 = +k) bit NB_OUT+f says the neighbour across f is outside the domain,
+// NB_INACTIVE+f that it is inactive, NB_SINK+f that it is a sink cell.  With
+// these the transfer to the next cell is decided from the current record.
+enum : int32_t {
+    CF_ACTIVE = 1,
+    CF_SINK = 2,
+    NB_OUT = 2,
+    NB_INACTIVE = 8,
+    NB_SINK = 14,
+};
+
+// 64-byte FP64 record: the six face velocities u = Q/(n V) (low/high face of
+// i, j, k) and the flag word.  64-byte aligned: one gather touches one half
+// of a 128-byte cache line.
+struct alignas(64) CellRec64 {
+    double u[6];
+    int32_t flags;
+    int32_t pad0;
+    double pad1;
+};
+static_assert(sizeof(CellRec64) == 64, "CellRec64 must be 64 bytes");
+
+// 32-byte FP32 record for the mixed-precision path.
+struct alignas(32) CellRec32 {
+    float u[6];
+    int32_t flags;
+    int32_t pad0;
+};
+static_assert(sizeof(CellRec32) == 32, "CellRec32 must be 32 bytes");
+
+// One flow field as the kernels see it.
+struct GridDev {
+    const CellRec64* rec64;
+    const CellRec32* rec32;
+    const double* qx;
+    const double* qy;
+    const double* qz;
+    const double* por;      // nullptr -> por_scalar
+    const int32_t* flags;   // own flags only (faces layout)
+    double por_scalar;
+    double dx, dy, dz, x0, y0, z0;
+    double V;               // (dx*dy)*dz
+    int32_t nx, ny, nz, pad;
+};
+
+// Counter block of a run (device), cleared by the reset kernel.
+struct Counters {
+    unsigned long long crossings;
+    unsigned long long status[8];
+    unsigned long long queue;       // next particle index handed out by the work queue
+    unsigned long long cr_ambiguous;  // correctly rounded evaluations left undecided
+    unsigned long long pad[5];
+};
+
+struct TrackParams {
+    int64_t n;
+    int32_t* cell;
+    double* xi;
+    double* eta;
+    double* zeta;
+    double* t;
+    int32_t* status;
+    int32_t* ncross;
+    uint64_t* hash;
+    // batched runs: device copies of the group table and of the grid views
+    const int64_t* group_offsets;
+    const int32_t* group_grid;
+    const GridDev* grids;
+    int32_t n_groups;
+    int32_t n_grids;
+    GridDev g0;             // grids[0], by value for single-grid runs
+    double t_max;
+    int64_t max_steps;
+    double sign;            // +1 forward, -1 backward
+    int32_t stop_at_sink;
+    int32_t n_snap;
+    const double* snap_times;
+    double* snap_xyz;
+    double* out_xyz;
+    Counters* counters;
+    int32_t refill;
+    int32_t steps_per_refill;
+};
+
+enum Precision { P64 = 0, PMIX = 1 };
+enum Layout { L_FACES = 1, L_CELL = 2 };
+enum Sched { S_STATIC = 1, S_PERSISTENT = 2 };
+
+struct KernelKey {
+    int precision, layout, timeseries, batched, sched;
+};
+
+// Kernel lookup (defined in pt_kernels.hip).
+const void* track_kernel(const KernelKey& k);
+const void* reset_kernel();
+const void* build_kernel();
+const void* check_kernel();
+
+// Grid build kernel arguments.
+struct BuildParams {
+    GridDev g;
+    CellRec64* rec64;
+    CellRec32* rec32;
+    double balance_tol;
+    int* err;               // [4]: non-finite flow, bad porosity, bad flags, unbalanced
+};
+
+constexpr int kMaxSnapLds = 1024;
+
+}  // namespace pt

@@ -1,0 +1,696 @@
+// Tracking kernels for gfx950 (CDNA4, wave64).
+//
+// The hot path of semi-analytical particle tracking (the paper: Introduction;
+// Methods, "MODPATH" and "Multiprocessing"): every particle is displaced cell
+// by cell, one analytic step per cell up to the earliest reachable face, and
+// is handed to the neighbour across that face until a stopping condition
+// (boundary face, maximum time, sink cell) holds.  Particles are independent,
+// so the kernels are data parallel over particles:
+//
+//   * static:     one thread per particle for its whole track (the analogue of
+//                 the paper's static scheduling, Methods "Multiprocessing");
+//   * persistent: resident waves pull particle indices from a device work
+//                 queue; lanes whose particle stopped are refilled at wave level
+//                 (ballot + mbcnt prefix count, one atomic per wave), so slow
+//                 particles do not idle a whole wave -- the device form of the
+//                 paper's dynamic scheduling (Methods "Multiprocessing",
+//                 Results "Thread scheduling").
+//
+// Per step (one cell crossing): gather the cell's six face velocities and its
+// flag word (one 64-byte record, or the face arrays), compute each axis' exit
+// time from the linear-velocity solution, take the earliest (ties to the lowest
+// axis), apply the time limit, advance the other axes analytically, and
+// transfer to the neighbour.  Compiled with -ffp-contract=off: no FMA
+// contraction, so the FP64 path rounds exactly as written.
+#include <math.h>
+
+#include "pt_crmath.h"
+#include "pt_internal.h"
+
+namespace pt {
+namespace {
+
+constexpr unsigned long long kFnvPrime = 0x100000001b3ull;
+constexpr int kBlock = 256;
+
+enum : int32_t {
+    ST_ACTIVE = 0,
+    ST_BOUNDARY = 1,
+    ST_SINK = 2,
+    ST_MAX_TIME = 3,
+    ST_STEP_CAP = 4,
+    ST_STRANDED = 5,
+    ST_INVALID = 6,
+    ST_INACTIVE_NB = 7,
+    ST_SKIP = -1,  // not tracked by this call (already terminated)
+};
+
+__device__ __forceinline__ double dinf() { return __builtin_huge_val(); }
+
+// ---------------------------------------------------------------------------------------------
+// One axis, FP64.  u1/u2: velocities at the low/high face (1/d), xi: local coordinate.
+// Exit time to the face the velocity points at; +inf when that face is never reached
+// (zero particle velocity, or a face velocity of zero or opposite sign).  The exit time
+// ln(u_e/u_p)/A is evaluated as (D/u_p) * log1p(x)/x with x = A D/u_p, which stays exact
+// as A -> 0; for x < -1/2 (strong deceleration) the ratio u_e/u_p is formed directly.
+// log1p, log and expm1 are correctly rounded (pt_crmath.h), so every FP64 operation of a
+// step has one defined result.  `amb` counts roundings the accurate phase could not decide.
+__device__ __forceinline__ double exit_time64(double u1, double u2, double xi, double& xe,
+                                              unsigned& amb) {
+    const double A = u2 - u1;
+    const double up = u1 + A * xi;
+    double ue;
+    if (up > 0.0) {
+        xe = 1.0;
+        ue = u2;
+        if (!(ue > 0.0)) return dinf();
+    } else if (up < 0.0) {
+        xe = 0.0;
+        ue = u1;
+        if (!(ue < 0.0)) return dinf();
+    } else {
+        return dinf();
+    }
+    const double D = xe - xi;
+    const double r = D / up;
+    const double x = A * r;
+    double dt;
+    if (x == 0.0) {
+        dt = r;
+    } else if (x < -0.5) {
+        dt = ptcr::log_cr(ue / up, &amb) / A;
+    } else {
+        dt = r * (ptcr::log1p_cr(x, &amb) / x);
+    }
+    if (dt < 0.0) dt = 0.0;
+    return dt;
+}
+
+// Position along one axis after tau: xi + u_p tau expm1(A tau)/(A tau), clamped to [0,1].
+__device__ __forceinline__ double adv64(double u1, double u2, double xi, double tau, unsigned& amb) {
+    const double A = u2 - u1;
+    const double up = u1 + A * xi;
+    if (up == 0.0) return xi;
+    const double y = A * tau;
+    const double psi = (y == 0.0) ? 1.0 : ptcr::expm1_cr(y, &amb) / y;
+    double xn = xi + (up * tau) * psi;
+    xn = (xn < 0.0) ? 0.0 : xn;
+    xn = (xn > 1.0) ? 1.0 : xn;
+    return xn;
+}
+
+// ---------------------------------------------------------------------------------------------
+// One axis, mixed precision: FP32 velocities and local coordinate; FP64 for the
+// near-zero-gradient branch (|x| < 2^-10 or |A tau| < 2^-10) and for time.
+constexpr float kNearZero = 0x1p-10f;
+
+__device__ __forceinline__ double exit_time_mix(float u1, float u2, float xi, float& xe, unsigned& amb) {
+    const float A = u2 - u1;
+    const float up = u1 + A * xi;
+    float ue;
+    if (up > 0.0f) {
+        xe = 1.0f;
+        ue = u2;
+        if (!(ue > 0.0f)) return dinf();
+    } else if (up < 0.0f) {
+        xe = 0.0f;
+        ue = u1;
+        if (!(ue < 0.0f)) return dinf();
+    } else {
+        return dinf();
+    }
+    const float D = xe - xi;
+    const float r = D / up;
+    const float x = A * r;
+    if (fabsf(x) < kNearZero) {
+        const double rd = (double)D / (double)up;
+        const double xd = (double)A * rd;
+        double dt = (xd == 0.0) ? rd : rd * (ptcr::log1p_cr(xd, &amb) / xd);
+        return dt < 0.0 ? 0.0 : dt;
+    }
+    float dt;
+    if (x < -0.5f) {
+        dt = logf(ue / up) / A;
+    } else {
+        dt = r * (log1pf(x) / x);
+    }
+    if (dt < 0.0f) dt = 0.0f;
+    return (double)dt;
+}
+
+__device__ __forceinline__ float adv_mix(float u1, float u2, float xi, double tau, unsigned& amb) {
+    const float A = u2 - u1;
+    const float up = u1 + A * xi;
+    if (up == 0.0f) return xi;
+    const float tf = (float)tau;
+    const float y = A * tf;
+    float xn;
+    if (fabsf(y) < kNearZero) {
+        const double yd = (double)A * tau;
+        const double psi = (yd == 0.0) ? 1.0 : ptcr::expm1_cr(yd, &amb) / yd;
+        xn = (float)((double)xi + ((double)up * tau) * psi);
+    } else {
+        xn = xi + (up * tf) * (expm1f(y) / y);
+    }
+    xn = (xn < 0.0f) ? 0.0f : xn;
+    xn = (xn > 1.0f) ? 1.0f : xn;
+    return xn;
+}
+
+// ---------------------------------------------------------------------------------------------
+template <int PREC> struct Real;
+template <> struct Real<P64> { using T = double; };
+template <> struct Real<PMIX> { using T = float; };
+
+template <int PREC>
+__device__ __forceinline__ double exit_time(typename Real<PREC>::T u1, typename Real<PREC>::T u2,
+                                            typename Real<PREC>::T xi, typename Real<PREC>::T& xe,
+                                            unsigned& amb) {
+    if constexpr (PREC == P64) return exit_time64(u1, u2, xi, xe, amb);
+    else return exit_time_mix(u1, u2, xi, xe, amb);
+}
+
+template <int PREC>
+__device__ __forceinline__ typename Real<PREC>::T adv(typename Real<PREC>::T u1,
+                                                      typename Real<PREC>::T u2,
+                                                      typename Real<PREC>::T xi, double tau,
+                                                      unsigned& amb) {
+    if constexpr (PREC == P64) return adv64(u1, u2, xi, tau, amb);
+    else return adv_mix(u1, u2, xi, tau, amb);
+}
+
+// Lane state of one particle.
+template <int PREC>
+struct Lane {
+    using R = typename Real<PREC>::T;
+    int64_t pid;        // particle index, -1 when the lane is idle
+    int32_t c, i, j, k; // cell
+    int32_t g;          // grid index (batched runs)
+    int32_t ncross;
+    int32_t ks;         // next snapshot index
+    unsigned amb;       // undecided roundings of the correctly rounded functions
+    unsigned long long hash;
+    double t;
+    double s_next;      // time of snapshot ks (+inf past the last)
+    R x[3];             // local coordinates
+};
+
+template <bool BATCHED>
+__device__ __forceinline__ const GridDev& grid_of(const TrackParams& P, int32_t g) {
+    if constexpr (BATCHED) return P.grids[g];
+    else return P.g0;
+}
+
+// Gather one cell: face velocities (with the direction sign) and the flag word.
+template <int PREC, int LAYOUT>
+__device__ __forceinline__ void load_cell(const GridDev& G, const Lane<PREC>& L, double sign,
+                                          typename Real<PREC>::T (&u1)[3],
+                                          typename Real<PREC>::T (&u2)[3], int32_t& fl) {
+    if constexpr (LAYOUT == L_CELL) {
+        if constexpr (PREC == P64) {
+            const double2* r = reinterpret_cast<const double2*>(G.rec64 + L.c);
+            const double2 a = r[0], b = r[1], d = r[2];
+            fl = G.rec64[L.c].flags;
+            u1[0] = sign * a.x; u2[0] = sign * a.y;
+            u1[1] = sign * b.x; u2[1] = sign * b.y;
+            u1[2] = sign * d.x; u2[2] = sign * d.y;
+        } else {
+            const float4* r = reinterpret_cast<const float4*>(G.rec32 + L.c);
+            const float4 a = r[0];
+            const float4 b = r[1];
+            const float fs = (float)sign;
+            fl = __float_as_int(b.z);
+            u1[0] = fs * a.x; u2[0] = fs * a.y;
+            u1[1] = fs * a.z; u2[1] = fs * a.w;
+            u1[2] = fs * b.x; u2[2] = fs * b.y;
+        }
+    } else {
+        static_assert(PREC == P64, "the faces layout is FP64 only");
+        const int64_t nx = G.nx, ny = G.ny;
+        const int64_t fx = ((int64_t)L.k * ny + L.j) * (nx + 1) + L.i;
+        const int64_t fy = ((int64_t)L.k * (ny + 1) + L.j) * nx + L.i;
+        const int64_t fz = ((int64_t)L.k * ny + L.j) * nx + L.i;
+        const double n_c = G.por ? G.por[L.c] : G.por_scalar;
+        const double d = n_c * G.V;
+        u1[0] = (sign * G.qx[fx]) / d;
+        u2[0] = (sign * G.qx[fx + 1]) / d;
+        u1[1] = (sign * G.qy[fy]) / d;
+        u2[1] = (sign * G.qy[fy + nx]) / d;
+        u1[2] = (sign * G.qz[fz]) / d;
+        u2[2] = (sign * G.qz[fz + nx * ny]) / d;
+        fl = G.flags[L.c];
+    }
+}
+
+__device__ __forceinline__ void put_nan3(double* p) {
+    const double q = __builtin_nan("");
+    p[0] = q;
+    p[1] = q;
+    p[2] = q;
+}
+
+// Global position of local coordinates (a, b, d) in cell (i, j, k).
+__device__ __forceinline__ void global_xyz(const GridDev& G, int32_t i, int32_t j, int32_t k, double a,
+                                           double b, double d, double* out) {
+    out[0] = G.x0 + ((double)i + a) * G.dx;
+    out[1] = G.y0 + ((double)j + b) * G.dy;
+    out[2] = G.z0 + ((double)k + d) * G.dz;
+}
+
+// Positions at the snapshot times s with s < to (or s <= to when closed), evaluated from the
+// state at the start of the step with tau = s - t.
+template <int PREC>
+__device__ __forceinline__ void write_snaps(Lane<PREC>& L, const GridDev& G,
+                                            const typename Real<PREC>::T (&u1)[3],
+                                            const typename Real<PREC>::T (&u2)[3],
+                                            const TrackParams& P, const double* snap, double to,
+                                            bool closed) {
+    double* row = P.snap_xyz + L.pid * (int64_t)P.n_snap * 3;
+    while (L.ks < P.n_snap) {
+        const double s = L.s_next;
+        if (closed ? !(s <= to) : !(s < to)) break;
+        const double tau = s - L.t;
+        const double a = (double)adv<PREC>(u1[0], u2[0], L.x[0], tau, L.amb);
+        const double b = (double)adv<PREC>(u1[1], u2[1], L.x[1], tau, L.amb);
+        const double d = (double)adv<PREC>(u1[2], u2[2], L.x[2], tau, L.amb);
+        global_xyz(G, L.i, L.j, L.k, a, b, d, row + 3 * (int64_t)L.ks);
+        ++L.ks;
+        L.s_next = (L.ks < P.n_snap) ? snap[L.ks] : dinf();
+    }
+}
+
+template <int PREC>
+__device__ __forceinline__ void nan_rest(Lane<PREC>& L, const TrackParams& P) {
+    double* row = P.snap_xyz + L.pid * (int64_t)P.n_snap * 3;
+    for (int32_t q = L.ks; q < P.n_snap; ++q) put_nan3(row + 3 * (int64_t)q);
+    L.ks = P.n_snap;
+}
+
+// Group of particle `pid` (largest g with group_offsets[g] <= pid, empty groups skipped).
+__device__ __forceinline__ int32_t find_group(const TrackParams& P, int64_t pid) {
+    int32_t lo = 0, hi = P.n_groups;  // invariant: offsets[lo] <= pid < offsets[hi]
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (P.group_offsets[mid] <= pid) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Release checks (S0).  Returns 0 when the particle is to be tracked, ST_SKIP when it is
+// not tracked by this call, or a final status.
+template <int PREC, int LAYOUT, bool TS, bool BATCHED>
+__device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap) {
+    using R = typename Real<PREC>::T;
+    const int64_t p = L.pid;
+    const int32_t st = P.status[p];
+    L.g = 0;
+    if constexpr (BATCHED) L.g = P.group_grid[find_group(P, p)];
+    const GridDev& G = grid_of<BATCHED>(P, L.g);
+    const int64_t ncell = (int64_t)G.nx * G.ny * G.nz;
+    const int32_t c = P.cell[p];
+    if (st != ST_ACTIVE && st != ST_MAX_TIME) {
+        if (P.out_xyz) {
+            double* o = P.out_xyz + 3 * p;
+            if (st == ST_INVALID || c < 0 || c >= ncell) {
+                put_nan3(o);
+            } else {
+                const int32_t plane = G.nx * G.ny;
+                const int32_t k = c / plane, rem = c - k * plane;
+                const int32_t j = rem / G.nx, i = rem - j * G.nx;
+                global_xyz(G, i, j, k, P.xi[p], P.eta[p], P.zeta[p], o);
+            }
+        }
+        return ST_SKIP;
+    }
+    const bool fresh = (st == ST_ACTIVE);
+    const double a = P.xi[p], b = P.eta[p], d = P.zeta[p], t = P.t[p];
+    bool bad = (c < 0 || (int64_t)c >= ncell);
+    int32_t own = 0;
+    if (!bad) {
+        if constexpr (LAYOUT == L_CELL) {
+            own = (PREC == P64) ? G.rec64[c].flags : G.rec32[c].flags;
+        } else {
+            own = G.flags[c];
+        }
+        bad = !(own & CF_ACTIVE);
+    }
+    if (!(a >= 0.0 && a <= 1.0) || !(b >= 0.0 && b <= 1.0) || !(d >= 0.0 && d <= 1.0)) bad = true;
+    if (!(t == t) || __builtin_isinf(t)) bad = true;
+    if (bad) {
+        if constexpr (TS) {
+            L.ks = 0;
+            nan_rest(L, P);
+        }
+        return ST_INVALID;
+    }
+    L.c = c;
+    const int32_t plane = G.nx * G.ny;
+    L.k = c / plane;
+    const int32_t rem = c - L.k * plane;
+    L.j = rem / G.nx;
+    L.i = rem - L.j * G.nx;
+    L.x[0] = (R)a;
+    L.x[1] = (R)b;
+    L.x[2] = (R)d;
+    L.t = t;
+    L.ncross = P.ncross[p];
+    L.hash = P.hash[p];
+    if constexpr (TS) {
+        double* row = P.snap_xyz + p * (int64_t)P.n_snap * 3;
+        int32_t q = 0;
+        while (q < P.n_snap && snap[q] < t) {
+            if (fresh) put_nan3(row + 3 * (int64_t)q);
+            ++q;
+        }
+        L.ks = q;
+        L.s_next = (q < P.n_snap) ? snap[q] : dinf();
+    }
+    if ((own & CF_SINK) && P.stop_at_sink) return ST_SINK;
+    if (t > P.t_max) return ST_MAX_TIME;
+    return 0;
+}
+
+// Write the final state of a tracked particle.
+template <int PREC, bool TS, bool BATCHED>
+__device__ void finish(Lane<PREC>& L, int32_t st, const TrackParams& P, unsigned int* s_hist) {
+    const int64_t p = L.pid;
+    P.status[p] = st;
+    atomicAdd(&s_hist[st], 1u);
+    if (st == ST_INVALID) {
+        if (P.out_xyz) put_nan3(P.out_xyz + 3 * p);
+        return;
+    }
+    P.cell[p] = L.c;
+    P.xi[p] = (double)L.x[0];
+    P.eta[p] = (double)L.x[1];
+    P.zeta[p] = (double)L.x[2];
+    P.t[p] = L.t;
+    P.ncross[p] = L.ncross;
+    P.hash[p] = L.hash;
+    if (P.out_xyz) {
+        const GridDev& G = grid_of<BATCHED>(P, L.g);
+        global_xyz(G, L.i, L.j, L.k, (double)L.x[0], (double)L.x[1], (double)L.x[2], P.out_xyz + 3 * p);
+    }
+    if constexpr (TS) nan_rest(L, P);
+}
+
+// One cell crossing (S1-S7).  Returns 0 to continue, or the final status.
+template <int PREC, int LAYOUT, bool TS, bool BATCHED>
+__device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& P, const double* snap,
+                                              unsigned long long& crossings) {
+    using R = typename Real<PREC>::T;
+    const GridDev& G = grid_of<BATCHED>(P, L.g);
+    R u1[3], u2[3];
+    int32_t fl;
+    load_cell<PREC, LAYOUT>(G, L, P.sign, u1, u2, fl);
+
+    // earliest reachable face; exact ties go to the lowest axis
+    double dt = dinf();
+    int32_t axis = -1;
+    R xe = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        R e = 0;
+        const double ta = exit_time<PREC>(u1[a], u2[a], L.x[a], e, L.amb);
+        if (ta < dt) {
+            dt = ta;
+            axis = a;
+            xe = e;
+        }
+    }
+
+    // time limit; a face reached exactly at t_max is crossed
+    if (axis < 0 && __builtin_isinf(P.t_max)) {
+        if constexpr (TS) write_snaps<PREC>(L, G, u1, u2, P, snap, dinf(), true);
+        return ST_STRANDED;
+    }
+    const double t_exit = L.t + dt;
+    if (t_exit > P.t_max) {
+        const double tau = P.t_max - L.t;
+        if constexpr (TS) write_snaps<PREC>(L, G, u1, u2, P, snap, P.t_max, true);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) L.x[a] = adv<PREC>(u1[a], u2[a], L.x[a], tau, L.amb);
+        L.t = P.t_max;
+        return axis < 0 ? ST_STRANDED : ST_MAX_TIME;
+    }
+
+    // advance to the exit face: the two other axes move analytically
+    if constexpr (TS) write_snaps<PREC>(L, G, u1, u2, P, snap, t_exit, false);
+    {
+        const int a1 = (axis == 0) ? 1 : 0;
+        const int a2 = (axis == 2) ? 1 : 2;
+        const R v1a = (a1 == 0) ? u1[0] : u1[1];
+        const R v2a = (a1 == 0) ? u2[0] : u2[1];
+        const R xa = (a1 == 0) ? L.x[0] : L.x[1];
+        const R v1b = (a2 == 1) ? u1[1] : u1[2];
+        const R v2b = (a2 == 1) ? u2[1] : u2[2];
+        const R xb = (a2 == 1) ? L.x[1] : L.x[2];
+        const R na = adv<PREC>(v1a, v2a, xa, dt, L.amb);
+        const R nb = adv<PREC>(v1b, v2b, xb, dt, L.amb);
+        L.x[0] = (axis == 0) ? xe : na;
+        L.x[1] = (axis == 1) ? xe : ((a1 == 1) ? na : nb);
+        L.x[2] = (axis == 2) ? xe : nb;
+    }
+    L.t = t_exit;
+    L.ncross += 1;
+    crossings += 1;
+    L.hash = (L.hash ^ (unsigned long long)(uint32_t)L.c) * kFnvPrime;
+
+    // transfer to the neighbour across the exit face
+    const int32_t hi = (xe == (R)1) ? 1 : 0;
+    const int32_t f = 2 * axis + hi;
+    const int32_t step = hi ? 1 : -1;
+    int32_t nfl_sink;
+    if constexpr (LAYOUT == L_CELL) {
+        if ((fl >> (NB_OUT + f)) & 1) return ST_BOUNDARY;
+        if ((fl >> (NB_INACTIVE + f)) & 1) return ST_INACTIVE_NB;
+        nfl_sink = (fl >> (NB_SINK + f)) & 1;
+    } else {
+        const int32_t ii = L.i + (axis == 0 ? step : 0);
+        const int32_t jj = L.j + (axis == 1 ? step : 0);
+        const int32_t kk = L.k + (axis == 2 ? step : 0);
+        if (ii < 0 || ii >= G.nx || jj < 0 || jj >= G.ny || kk < 0 || kk >= G.nz) return ST_BOUNDARY;
+        const int32_t nfl = G.flags[(kk * G.ny + jj) * G.nx + ii];
+        if (!(nfl & CF_ACTIVE)) return ST_INACTIVE_NB;
+        nfl_sink = (nfl & CF_SINK) ? 1 : 0;
+    }
+    if (axis == 0) {
+        L.i += step;
+        L.c += step;
+    } else if (axis == 1) {
+        L.j += step;
+        L.c += step * G.nx;
+    } else {
+        L.k += step;
+        L.c += step * G.nx * G.ny;
+    }
+    L.x[0] = (axis == 0) ? (R)1 - xe : L.x[0];
+    L.x[1] = (axis == 1) ? (R)1 - xe : L.x[1];
+    L.x[2] = (axis == 2) ? (R)1 - xe : L.x[2];
+    if (nfl_sink && P.stop_at_sink) return ST_SINK;
+    if ((int64_t)L.ncross >= P.max_steps) return ST_STEP_CAP;
+    return 0;
+}
+
+// Block-level setup shared by both kernels: LDS snapshot copy and counters.
+struct BlockShared {
+    double snap[kMaxSnapLds];
+    unsigned int hist[8];
+    unsigned long long cross;
+    unsigned int amb;
+};
+
+template <bool TS>
+__device__ __forceinline__ const double* block_setup(BlockShared& S, const TrackParams& P) {
+    if (threadIdx.x < 8) S.hist[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) {
+        S.cross = 0ull;
+        S.amb = 0u;
+    }
+    const double* snap = P.snap_times;
+    if constexpr (TS) {
+        if (P.n_snap <= kMaxSnapLds) {
+            for (int q = threadIdx.x; q < P.n_snap; q += blockDim.x) S.snap[q] = P.snap_times[q];
+            snap = S.snap;
+        }
+    }
+    __syncthreads();
+    return snap;
+}
+
+__device__ __forceinline__ void block_flush(BlockShared& S, const TrackParams& P,
+                                            unsigned long long crossings, unsigned amb) {
+    // wave-level reduction of the crossing count, one LDS atomic per wave
+    for (int off = 32; off > 0; off >>= 1) crossings += __shfl_down(crossings, off, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&S.cross, crossings);
+    if (amb) atomicAdd(&S.amb, amb);
+    __syncthreads();
+    if (threadIdx.x == 0 && S.amb) atomicAdd(&P.counters->cr_ambiguous, (unsigned long long)S.amb);
+    if (threadIdx.x < 8 && S.hist[threadIdx.x])
+        atomicAdd(&P.counters->status[threadIdx.x], (unsigned long long)S.hist[threadIdx.x]);
+    if (threadIdx.x == 0 && S.cross) atomicAdd(&P.counters->crossings, S.cross);
+}
+
+// ---------------------------------------------------------------------------------------------
+template <int PREC, int LAYOUT, bool TS, bool BATCHED>
+__global__ void __launch_bounds__(kBlock) k_track_static(TrackParams P) {
+    __shared__ BlockShared S;
+    const double* snap = block_setup<TS>(S, P);
+    unsigned long long crossings = 0;
+    Lane<PREC> L;
+    L.amb = 0u;
+    L.pid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (L.pid < P.n) {
+        int32_t st = begin<PREC, LAYOUT, TS, BATCHED>(L, P, snap);
+        while (st == 0) st = track_step<PREC, LAYOUT, TS, BATCHED>(L, P, snap, crossings);
+        if (st > 0) finish<PREC, TS, BATCHED>(L, st, P, S.hist);
+    }
+    block_flush(S, P, crossings, L.amb);
+}
+
+template <int PREC, int LAYOUT, bool TS, bool BATCHED>
+__global__ void __launch_bounds__(kBlock) k_track_persistent(TrackParams P) {
+    __shared__ BlockShared S;
+    const double* snap = block_setup<TS>(S, P);
+    unsigned long long crossings = 0;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long n = (unsigned long long)P.n;
+    const int refill = P.refill;
+    const int steps = P.steps_per_refill;
+    bool exhausted = false;  // wave-uniform
+    Lane<PREC> L;
+    L.amb = 0u;
+    L.pid = -1;
+    for (;;) {
+        const unsigned long long idle = __ballot(L.pid < 0);
+        const int nidle = __popcll(idle);
+        if (!exhausted && nidle >= refill) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(&P.counters->queue, (unsigned long long)nidle);
+            base = __shfl(base, 0, 64);
+            if (base + (unsigned long long)nidle >= n) exhausted = true;
+            if (L.pid < 0) {
+                const unsigned long long slot =
+                    base + __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+                if (slot < n) {
+                    L.pid = (int64_t)slot;
+                    const int32_t st = begin<PREC, LAYOUT, TS, BATCHED>(L, P, snap);
+                    if (st != 0) {
+                        if (st > 0) finish<PREC, TS, BATCHED>(L, st, P, S.hist);
+                        L.pid = -1;
+                    }
+                }
+            }
+        }
+        if (__ballot(L.pid >= 0) == 0ull) {
+            if (exhausted) break;
+            continue;
+        }
+        for (int s = 0; s < steps; ++s) {
+            if (L.pid >= 0) {
+                const int32_t st = track_step<PREC, LAYOUT, TS, BATCHED>(L, P, snap, crossings);
+                if (st != 0) {
+                    finish<PREC, TS, BATCHED>(L, st, P, S.hist);
+                    L.pid = -1;
+                }
+            }
+        }
+    }
+    block_flush(S, P, crossings, L.amb);
+}
+
+__global__ void k_reset(Counters* c) {
+    unsigned long long* w = reinterpret_cast<unsigned long long*>(c);
+    const int n = sizeof(Counters) / sizeof(unsigned long long);
+    if ((int)threadIdx.x < n) w[threadIdx.x] = 0ull;
+}
+
+// Grid load: validate the field and build both packed records of every cell.
+__global__ void __launch_bounds__(256) k_build(BuildParams B) {
+    const GridDev& G = B.g;
+    const int64_t ncell = (int64_t)G.nx * G.ny * G.nz;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const int64_t nx = G.nx, ny = G.ny, nz = G.nz;
+    const int64_t plane = nx * ny;
+    const int64_t k = c / plane, rem = c - k * plane;
+    const int64_t j = rem / nx, i = rem - j * nx;
+    const int64_t fx = (k * ny + j) * (nx + 1) + i;
+    const int64_t fy = (k * (ny + 1) + j) * nx + i;
+    const int64_t fz = (k * ny + j) * nx + i;
+    const double q[6] = {G.qx[fx], G.qx[fx + 1], G.qy[fy], G.qy[fy + nx], G.qz[fz], G.qz[fz + plane]};
+    const double n_c = G.por ? G.por[c] : G.por_scalar;
+    const int32_t own = G.flags ? G.flags[c] : CF_ACTIVE;
+    bool finite = true;
+    for (int f = 0; f < 6; ++f) finite = finite && __builtin_isfinite(q[f]);
+    if (!finite) atomicOr(&B.err[0], 1);
+    if (!(n_c > 0.0) || !__builtin_isfinite(n_c)) atomicOr(&B.err[1], 1);
+    if (own & ~(CF_ACTIVE | CF_SINK)) atomicOr(&B.err[2], 1);
+    if (B.balance_tol >= 0.0 && (own & CF_ACTIVE) && !(own & CF_SINK) && finite) {
+        const double net = (q[0] - q[1]) + (q[2] - q[3]) + (q[4] - q[5]);
+        const double gross = fabs(q[0]) + fabs(q[1]) + fabs(q[2]) + fabs(q[3]) + fabs(q[4]) + fabs(q[5]);
+        if (fabs(net) > B.balance_tol * gross) atomicOr(&B.err[3], 1);
+    }
+    const double d = n_c * G.V;
+    int32_t word = own & (CF_ACTIVE | CF_SINK);
+    const int64_t ncoord[3] = {i, j, k};
+    const int64_t ndim[3] = {nx, ny, nz};
+    const int64_t nstride[3] = {1, nx, plane};
+    for (int f = 0; f < 6; ++f) {
+        const int a = f >> 1;
+        const int64_t s = (f & 1) ? 1 : -1;
+        const int64_t cc = ncoord[a] + s;
+        if (cc < 0 || cc >= ndim[a]) {
+            word |= 1 << (NB_OUT + f);
+        } else {
+            const int32_t nf = G.flags ? G.flags[c + s * nstride[a]] : CF_ACTIVE;
+            if (!(nf & CF_ACTIVE)) word |= 1 << (NB_INACTIVE + f);
+            if (nf & CF_SINK) word |= 1 << (NB_SINK + f);
+        }
+    }
+    CellRec64 r64;
+    CellRec32 r32;
+    for (int f = 0; f < 6; ++f) {
+        const double u = q[f] / d;
+        r64.u[f] = u;
+        r32.u[f] = (float)u;
+    }
+    r64.flags = word;
+    r64.pad0 = 0;
+    r64.pad1 = 0.0;
+    r32.flags = word;
+    r32.pad0 = 0;
+    B.rec64[c] = r64;
+    B.rec32[c] = r32;
+}
+
+template <int PREC, int LAYOUT, bool TS, bool BATCHED>
+const void* pick_sched(int sched) {
+    if (sched == S_STATIC) return reinterpret_cast<const void*>(&k_track_static<PREC, LAYOUT, TS, BATCHED>);
+    return reinterpret_cast<const void*>(&k_track_persistent<PREC, LAYOUT, TS, BATCHED>);
+}
+
+template <int PREC, int LAYOUT, bool TS>
+const void* pick_batched(const KernelKey& k) {
+    return k.batched ? pick_sched<PREC, LAYOUT, TS, true>(k.sched) : pick_sched<PREC, LAYOUT, TS, false>(k.sched);
+}
+
+template <int PREC, int LAYOUT>
+const void* pick_ts(const KernelKey& k) {
+    return k.timeseries ? pick_batched<PREC, LAYOUT, true>(k) : pick_batched<PREC, LAYOUT, false>(k);
+}
+
+}  // namespace
+
+const void* track_kernel(const KernelKey& k) {
+    if (k.precision == PMIX) return pick_ts<PMIX, L_CELL>(k);
+    if (k.layout == L_FACES) return pick_ts<P64, L_FACES>(k);
+    return pick_ts<P64, L_CELL>(k);
+}
+
+const void* reset_kernel() { return reinterpret_cast<const void*>(&k_reset); }
+const void* build_kernel() { return reinterpret_cast<const void*>(&k_build); }
+
+}  // namespace pt

@@ -1,0 +1,304 @@
+"""Python binding of libpt (the C ABI in include/pt.h): argument marshalling only.
+
+Every tracking step runs in the HIP kernels of libpt.so; this module converts
+arguments and owns nothing but torch tensors for device memory.  It raises
+ImportError when libpt.so has not been built -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # loads the HIP runtime that libpt shares with torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpt.so")
+
+PT_OK = 0
+ERR_NAMES = {-1: "PT_ERR_INVALID_ARG", -2: "PT_ERR_BAD_HANDLE", -3: "PT_ERR_OOM", -4: "PT_ERR_NO_DEVICE",
+             -5: "PT_ERR_DEVICE", -6: "PT_ERR_UNBALANCED", -7: "PT_ERR_UNSUPPORTED"}
+STATUS_NAMES = ["ACTIVE", "BOUNDARY", "SINK", "MAX_TIME", "STEP_CAP", "STRANDED", "INVALID_START",
+                "INACTIVE_NEIGHBOR"]
+PT_MEM_HOST, PT_MEM_DEVICE = 0, 1
+PT_ENDPOINT, PT_TIMESERIES = 0, 1
+PT_FP64, PT_MIXED = 0, 1
+PT_SCHED_AUTO, PT_SCHED_STATIC, PT_SCHED_PERSISTENT = 0, 1, 2
+PT_LAYOUT_AUTO, PT_LAYOUT_FACES, PT_LAYOUT_CELL = 0, 1, 2
+FNV_OFFSET = 0xCBF29CE484222325
+
+_p = ctypes.c_void_p
+
+
+class pt_grid_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("z0", ctypes.c_double),
+                ("qx", _p), ("qy", _p), ("qz", _p), ("porosity", _p),
+                ("porosity_scalar", ctypes.c_double), ("flags", _p), ("mem", ctypes.c_int32),
+                ("balance_tol", ctypes.c_double)]
+
+
+class pt_particles(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("cell", _p), ("xi", _p), ("eta", _p), ("zeta", _p), ("t", _p),
+                ("status", _p), ("ncross", _p), ("path_hash", _p), ("n_groups", ctypes.c_int32),
+                ("group_offsets", _p), ("group_grid", _p)]
+
+
+class pt_track_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("precision", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("layout", ctypes.c_int32), ("direction", ctypes.c_int32),
+                ("stop_at_sink", ctypes.c_int32), ("t_max", ctypes.c_double),
+                ("max_steps", ctypes.c_int64), ("snap_times", _p), ("n_snap", ctypes.c_int32),
+                ("snap_xyz", _p), ("out_xyz", _p), ("use_graph", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("refill", ctypes.c_int32), ("steps_per_refill", ctypes.c_int32)]
+
+
+class pt_summary(ctypes.Structure):
+    _fields_ = [("crossings", ctypes.c_int64), ("n_tracked", ctypes.c_int64),
+                ("status_count", ctypes.c_int64 * 8), ("kernel_ms", ctypes.c_double),
+                ("schedule", ctypes.c_int32), ("layout", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("cr_ambiguous", ctypes.c_int64)]
+
+
+EXPORTS = ["pt_load_grid", "pt_track", "pt_results", "pt_release", "pt_last_error", "pt_default_opts",
+           "pt_version"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpt.so (built by ``python -m paper_2302_13590_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libpt.so is not built (%s); run: python -m paper_2302_13590_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    lib.pt_load_grid.argtypes = [ctypes.POINTER(pt_grid_desc), _p, ctypes.POINTER(_p)]
+    lib.pt_load_grid.restype = ctypes.c_int
+    lib.pt_track.argtypes = [ctypes.POINTER(_p), ctypes.c_int32, ctypes.POINTER(pt_particles),
+                             ctypes.POINTER(pt_track_opts), _p, ctypes.POINTER(_p)]
+    lib.pt_track.restype = ctypes.c_int
+    lib.pt_results.argtypes = [_p, ctypes.POINTER(pt_summary)]
+    lib.pt_results.restype = ctypes.c_int
+    lib.pt_release.argtypes = [_p]
+    lib.pt_release.restype = ctypes.c_int
+    lib.pt_last_error.argtypes = []
+    lib.pt_last_error.restype = ctypes.c_char_p
+    lib.pt_default_opts.argtypes = [ctypes.POINTER(pt_track_opts)]
+    lib.pt_default_opts.restype = None
+    lib.pt_version.argtypes = []
+    lib.pt_version.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class PtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (ERR_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+def _check(rc: int):
+    if rc != PT_OK:
+        raise PtError(rc, pt_last_error())
+
+
+def pt_last_error() -> str:
+    return load_library().pt_last_error().decode()
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# --------------------------------------------------------------------------------------------- grid
+
+class Grid:
+    """Handle of a flow field loaded with pt_load_grid."""
+
+    def __init__(self, handle: int, nx: int, ny: int, nz: int):
+        self.handle = handle
+        self.shape = (nz, ny, nx)
+
+    def release(self):
+        if self.handle:
+            pt_release(self.handle)
+            self.handle = None
+
+
+def _ptr(a) -> Optional[int]:
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def pt_load_grid(grid, stream=None, balance_tol: float = -1.0) -> Grid:
+    """Load a grid (an object with nx, ny, nz, dx.., x0.., qx, qy, qz, flags, porosity,
+    porosity_scalar; numpy arrays -> host copy, CUDA tensors -> device copy)."""
+    lib = load_library()
+    arrs = [grid.qx, grid.qy, grid.qz, grid.porosity, grid.flags]
+    dev = any(isinstance(a, torch.Tensor) and a.is_cuda for a in arrs if a is not None)
+    keep = []
+
+    def conv(a, dtype):
+        if a is None:
+            return None
+        if isinstance(a, torch.Tensor):
+            a = a.contiguous()
+        else:
+            a = np.ascontiguousarray(a, dtype=dtype)
+        keep.append(a)
+        return _ptr(a)
+
+    d = pt_grid_desc(grid.nx, grid.ny, grid.nz, grid.dx, grid.dy, grid.dz, grid.x0, grid.y0, grid.z0,
+                     conv(grid.qx, np.float64), conv(grid.qy, np.float64), conv(grid.qz, np.float64),
+                     conv(grid.porosity, np.float64), grid.porosity_scalar, conv(grid.flags, np.int32),
+                     PT_MEM_DEVICE if dev else PT_MEM_HOST, balance_tol)
+    out = _p()
+    _check(lib.pt_load_grid(ctypes.byref(d), _stream_ptr(stream), ctypes.byref(out)))
+    return Grid(out.value, grid.nx, grid.ny, grid.nz)
+
+
+def pt_release(handle) -> None:
+    if isinstance(handle, (Grid, Run)):
+        h = handle.handle
+        handle.handle = None
+    else:
+        h = handle
+    _check(load_library().pt_release(h))
+
+
+# --------------------------------------------------------------------------------------------- particles
+
+@dataclasses.dataclass
+class DeviceParticles:
+    """Particle state as device tensors (the caller-owned in/out arrays of pt_particles)."""
+    cell: torch.Tensor
+    xi: torch.Tensor
+    eta: torch.Tensor
+    zeta: torch.Tensor
+    t: torch.Tensor
+    status: torch.Tensor
+    ncross: torch.Tensor
+    path_hash: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.cell.shape[0])
+
+    @staticmethod
+    def from_numpy(p, device="cuda") -> "DeviceParticles":
+        def T(a, dt):
+            return torch.from_numpy(np.ascontiguousarray(a).view(dt)).to(device)
+        return DeviceParticles(T(p.cell, np.int32), T(p.xi, np.float64), T(p.eta, np.float64),
+                               T(p.zeta, np.float64), T(p.t, np.float64), T(p.status, np.int32),
+                               T(p.ncross, np.int32), T(np.asarray(p.path_hash, np.uint64), np.int64))
+
+    def copy_(self, other: "DeviceParticles") -> "DeviceParticles":
+        for f in dataclasses.fields(self):
+            getattr(self, f.name).copy_(getattr(other, f.name), non_blocking=True)
+        return self
+
+    def clone(self) -> "DeviceParticles":
+        return DeviceParticles(*(getattr(self, f.name).clone() for f in dataclasses.fields(self)))
+
+    def to_numpy(self) -> dict:
+        out = {f.name: getattr(self, f.name).cpu().numpy() for f in dataclasses.fields(self)}
+        out["path_hash"] = out["path_hash"].view(np.uint64)
+        return out
+
+
+class Run:
+    def __init__(self, handle: int, keep):
+        self.handle = handle
+        self._keep = keep   # host arrays referenced by the call
+
+    def release(self):
+        if self.handle:
+            pt_release(self.handle)
+            self.handle = None
+
+
+def pt_default_opts() -> pt_track_opts:
+    o = pt_track_opts()
+    load_library().pt_default_opts(ctypes.byref(o))
+    return o
+
+
+def make_opts(mode=PT_ENDPOINT, precision=PT_FP64, schedule=PT_SCHED_AUTO, layout=PT_LAYOUT_AUTO,
+              direction=1, stop_at_sink=1, t_max=math.inf, max_steps=1 << 20, snap_times=None,
+              snap_xyz=None, out_xyz=None, use_graph=0, block=0, blocks_per_cu=0, refill=0,
+              steps_per_refill=0):
+    o = pt_default_opts()
+    o.mode, o.precision, o.schedule, o.layout = mode, precision, schedule, layout
+    o.direction, o.stop_at_sink, o.t_max, o.max_steps = direction, stop_at_sink, t_max, max_steps
+    keep = []
+    if snap_times is not None:
+        st = np.ascontiguousarray(snap_times, dtype=np.float64)
+        keep.append(st)
+        o.snap_times = st.ctypes.data
+        o.n_snap = st.shape[0]
+    o.snap_xyz = _ptr(snap_xyz)
+    o.out_xyz = _ptr(out_xyz)
+    o.use_graph, o.block, o.blocks_per_cu, o.refill, o.steps_per_refill = (
+        use_graph, block, blocks_per_cu, refill, steps_per_refill)
+    o._keep = keep
+    return o
+
+
+def pt_track(grids: Sequence[Grid], particles: DeviceParticles, opts: pt_track_opts, stream=None,
+             group_offsets=None, group_grid=None) -> Run:
+    """Enqueue tracking; returns a Run (call pt_results, then pt_release)."""
+    lib = load_library()
+    handles = (_p * len(grids))(*[g.handle for g in grids])
+    keep = [handles, opts]
+    pp = pt_particles()
+    pp.n = particles.n
+    for name in ("cell", "xi", "eta", "zeta", "t", "status", "ncross", "path_hash"):
+        setattr(pp, name, getattr(particles, name).data_ptr())
+    if group_offsets is not None:
+        go = np.ascontiguousarray(group_offsets, dtype=np.int64)
+        gg = np.ascontiguousarray(group_grid, dtype=np.int32)
+        keep += [go, gg]
+        pp.n_groups = gg.shape[0]
+        pp.group_offsets = go.ctypes.data
+        pp.group_grid = gg.ctypes.data
+    out = _p()
+    _check(lib.pt_track(handles, len(grids), ctypes.byref(pp), ctypes.byref(opts), _stream_ptr(stream),
+                        ctypes.byref(out)))
+    return Run(out.value, keep)
+
+
+def pt_results(run: Run) -> dict:
+    s = pt_summary()
+    _check(load_library().pt_results(run.handle, ctypes.byref(s)))
+    return dict(crossings=s.crossings, n_tracked=s.n_tracked, status_count=list(s.status_count),
+                kernel_ms=s.kernel_ms, schedule=s.schedule, layout=s.layout, block=s.block, grid=s.grid,
+                cr_ambiguous=s.cr_ambiguous)
+
+
+# --------------------------------------------------------------------------------------------- helper
+
+def track(grids, particles: DeviceParticles, stream=None, group_offsets=None, group_grid=None,
+          **opt) -> dict:
+    """pt_track + pt_results + pt_release in one call; returns the summary."""
+    o = make_opts(**opt)
+    run = pt_track(grids, particles, o, stream=stream, group_offsets=group_offsets, group_grid=group_grid)
+    try:
+        return pt_results(run)
+    finally:
+        run.release()

@@ -251,7 +251,7 @@ def pin_outflow_exits(lib):
     g = _rand_grid()
     rng = np.random.Generator(np.random.PCG64(5))
     p = C.release(rng, 300, g.nx, g.ny, g.nz)
-    r = O.track(g, p, path_cap=256, lib=lib)
+    r = O.track(g, p, path_cap=256, max_steps=5000, lib=lib)
     assert set(np.unique(r.status)) <= {BOUNDARY, SINK}
     nx, ny = g.nx, g.ny
     for q in range(p.n):
@@ -280,11 +280,11 @@ def pin_reversibility(lib):
     rng = np.random.Generator(np.random.PCG64(9))
     p = C.release(rng, 200, g.nx, g.ny, g.nz, i_range=(0, 2))
     T = 4.0
-    f = O.track(g, p, t_max=T, path_cap=256, lib=lib)
+    f = O.track(g, p, t_max=T, path_cap=256, max_steps=5000, lib=lib)
     keep = f.status == MAX_TIME
     assert keep.sum() > 50
     back = H.particles(f.cell, f.xi, f.eta, f.zeta)
-    b = O.track(g, back, direction=-1, t_max=T, path_cap=256, lib=lib)
+    b = O.track(g, back, direction=-1, t_max=T, path_cap=256, max_steps=5000, lib=lib)
     for q in np.nonzero(keep)[0]:
         assert b.status[q] == MAX_TIME and b.cell[q] == p.cell[q], q
         for a, (x1, x0) in enumerate(((b.xi, p.xi), (b.eta, p.eta), (b.zeta, p.zeta))):
@@ -317,7 +317,8 @@ def pin_resume(lib):
 def _rk4_compare(lib, g, n, seed, snaps=()):
     rng = np.random.Generator(np.random.PCG64(seed))
     p = C.release(rng, n, g.nx, g.ny, g.nz)
-    r = O.track(g, p, path_cap=512, snap_times=np.array(snaps) if len(snaps) else None, lib=lib)
+    r = O.track(g, p, path_cap=512, snap_times=np.array(snaps) if len(snaps) else None, max_steps=5000,
+                lib=lib)
     scale = max(g.dx, g.dy, g.dz)
     for q in range(n):
         cr, fin, sn = H.rk4_track(g, int(p.cell[q]), (p.xi[q], p.eta[q], p.zeta[q]),

@@ -26,7 +26,7 @@ MUTANTS = {
     "no_flip_on_transfer": ("loc[axis] = 1.0 - xe;", "loc[axis] = xe;"),
     "y_scaled_by_dz": ("out[1] = g->y0 + ((double)j + eta) * g->dy;",
                        "out[1] = g->y0 + ((double)j + eta) * g->dz;"),
-    "exit_time_without_log": ("dt = r * (log1p(x) / x);", "dt = r;"),
+    "exit_time_without_log": ("dt = r * (cr_log1p(x) / x);", "dt = r;"),
     "no_ratio_branch": ("} else if (x < -0.5) {", "} else if (x < -2.0) {"),
     "non_strict_time_limit": ("if (t_exit > o->t_max) {", "if (t_exit >= o->t_max) {"),
     "scalar_porosity_only": ("double n_c = g->porosity ? g->porosity[c] : g->porosity_scalar;",
@@ -34,7 +34,7 @@ MUTANTS = {
     "wrong_hash_prime": ("0x100000001b3ULL", "0x100000001b5ULL"),
     "transposed_neighbour": ("int64_t cn = (kk * g->ny + jj) * g->nx + ii;",
                              "int64_t cn = (kk * g->nx + jj) * g->ny + ii;"),
-    "advance_without_exp": ("double psi = (y == 0.0) ? 1.0 : expm1(y) / y;", "double psi = 1.0;"),
+    "advance_without_exp": ("double psi = (y == 0.0) ? 1.0 : cr_expm1(y) / y;", "double psi = 1.0;"),
     "snapshot_from_zero": ("double tau = s - t;", "double tau = s;"),
     "no_sink_stop_on_entry": ("        if ((g->flags[c] & CELL_SINK) && o->stop_at_sink) {\n"
                               "            status_[p] = ST_SINK;\n            break;\n        }\n", ""),

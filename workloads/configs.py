@@ -28,6 +28,7 @@ This module generates inputs only; it contains none of the tracking arithmetic.
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 from typing import Optional
 
@@ -146,6 +147,7 @@ def c1(n: int = 1000) -> Workload:
     return Workload("C1", [g], p)
 
 
+@functools.lru_cache(maxsize=32)
 def c2_grid(realization: int = 0, sigma2: float = 1.0, cfg: int = 2) -> Grid:
     K = kfield.lognormal_k((10, 100, 100), 10.0, sigma2, 5.0, 1000 * cfg + realization)
     return make_grid(K, 10.0, 10.0, 2.0, meta=dict(name="C%d/r%d" % (cfg, realization), sigma2=sigma2))
@@ -161,6 +163,7 @@ def c2(n: int = 1_000_000) -> Workload:
 WELLS_C3 = ((66, 100), (133, 100))   # (i, j) columns, all layers
 
 
+@functools.lru_cache(maxsize=32)
 def c3_grid() -> Grid:
     shape = (20, 200, 200)
     K = kfield.lognormal_k(shape, 10.0, 4.0, 8.0, 1000 * 3)
@@ -209,6 +212,7 @@ def c5_snap_times(n_snap: int = 100) -> np.ndarray:
     return 10.0 ** (5.0 * k / (n_snap - 1))
 
 
+@functools.lru_cache(maxsize=32)
 def c5_grid() -> Grid:
     K = kfield.lognormal_k((20, 200, 200), 10.0, 2.0, 8.0, 1000 * 5)
     return make_grid(K, 10.0, 10.0, 2.0, meta=dict(name="C5", sigma2=2.0))
