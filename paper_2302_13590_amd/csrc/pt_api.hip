@@ -12,7 +12,7 @@
 #include <unordered_set>
 #include <vector>
 
-#include "../../include/pt.h"
+#include "pt.h"
 #include "pt_internal.h"
 
 using namespace pt;

@@ -28,15 +28,52 @@
 #ifdef __HIPCC__
 #include <hip/hip_runtime.h>
 #define PT_CR_HD __host__ __device__ inline
+#define PT_CR_COLD __host__ __device__ inline
 #define PT_CR_TABLE static constexpr
 #else
 #define PT_CR_HD static inline
+#define PT_CR_COLD static inline
 #define PT_CR_TABLE static constexpr
 #endif
 
 #include "pt_crtables.h"
 
 namespace ptcr {
+
+// Table access.  In device code the tables of the quick phase live in LDS (copied once
+// per workgroup by lds_tables_init): an LDS read is short and is counted apart from
+// global memory loads, so the tables never make a wave wait for an outstanding gather.
+#if defined(__HIP_DEVICE_COMPILE__)
+__shared__ double lds_log_c[PT_CR_LOG_J1 - PT_CR_LOG_J0 + 1];
+__shared__ double lds_log_l[PT_CR_LOG_J1 - PT_CR_LOG_J0 + 1][2];
+__shared__ double lds_exp_t[128][2];
+#define PT_CR_LOGC(i) (::ptcr::lds_log_c[(i)])
+#define PT_CR_LOGL(i, h) (::ptcr::lds_log_l[(i)][(h)])
+#define PT_CR_EXPT(i, h) (::ptcr::lds_exp_t[(i)][(h)])
+#else
+#define PT_CR_LOGC(i) (PT_CR_LOG_C[(i)])
+#define PT_CR_LOGL(i, h) (PT_CR_LOG_L[(i)][(h)])
+#define PT_CR_EXPT(i, h) (PT_CR_EXP_T[(i)][(h)])
+#endif
+
+#ifdef __HIPCC__
+// Copy the quick-phase tables into this workgroup's LDS; the caller synchronises the
+// workgroup before the first evaluation.
+__device__ inline void lds_tables_init() {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int n = PT_CR_LOG_J1 - PT_CR_LOG_J0 + 1;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        lds_log_c[q] = PT_CR_LOG_C[q];
+        lds_log_l[q][0] = PT_CR_LOG_L[q][0];
+        lds_log_l[q][1] = PT_CR_LOG_L[q][1];
+    }
+    for (int q = threadIdx.x; q < 128; q += blockDim.x) {
+        lds_exp_t[q][0] = PT_CR_EXP_T[q][0];
+        lds_exp_t[q][1] = PT_CR_EXP_T[q][1];
+    }
+#endif
+}
+#endif
 
 struct dd {
     double h, l;
@@ -121,7 +158,7 @@ PT_CR_HD LogRed log_reduce(double yh, double yl) {
     }
     const double ml = ldexp(yl, -e);
     const int j = (int)rint(m * 256.0);
-    const double c = PT_CR_LOG_C[j - PT_CR_LOG_J0];
+    const double c = PT_CR_LOGC(j - PT_CR_LOG_J0);
     const dd p = two_prod(m, c);              // exact
     dd r = fast_two_sum(p.h - 1.0, p.l);      // p.h - 1 is exact
     r = dd_add(r, two_prod(ml, c));
@@ -132,7 +169,7 @@ PT_CR_HD dd log_sum(const LogRed& R, dd p) {
     const double kd = (double)R.k;
     dd kl = two_prod(kd, PT_CR_LN2_H);
     kl.l = fma(kd, PT_CR_LN2_L, kl.l);
-    const dd L = {PT_CR_LOG_L[R.j - PT_CR_LOG_J0][0], PT_CR_LOG_L[R.j - PT_CR_LOG_J0][1]};
+    const dd L = {PT_CR_LOGL(R.j - PT_CR_LOG_J0, 0), PT_CR_LOGL(R.j - PT_CR_LOG_J0, 1)};
     return dd_add(kl, dd_add(L, p));
 }
 
@@ -171,15 +208,22 @@ PT_CR_HD dd log1p_series_accurate(dd r) {
     return dd_mul(r, S);
 }
 
+// Accurate phase: it runs for about one evaluation in 2^15.
+PT_CR_COLD double log_accurate(double yh, double yl, unsigned* ambiguous) {
+    const LogRed R = log_reduce(yh, yl);
+    const dd a = log_sum(R, log1p_series_accurate(R.r));
+    double out;
+    if (round_test(a, kEpsAccurate, &out)) return out;
+    *ambiguous += 1u;
+    return a.h + a.l;
+}
+
 PT_CR_HD double log_dd_cr(double yh, double yl, unsigned* ambiguous) {
     const LogRed R = log_reduce(yh, yl);
     double out;
     const dd q = log_sum(R, log1p_series_quick(R.r));
     if (round_test(q, kEpsQuick, &out)) return out;
-    const dd a = log_sum(R, log1p_series_accurate(R.r));
-    if (round_test(a, kEpsAccurate, &out)) return out;
-    *ambiguous += 1u;
-    return a.h + a.l;
+    return log_accurate(yh, yl, ambiguous);
 }
 
 // Correctly rounded log1p(x).
@@ -250,10 +294,22 @@ PT_CR_HD dd expm1_series_accurate(dd r) {
 PT_CR_HD dd expm1_combine(const ExpRed& R, dd q, int s) {
     if (R.k == 0 && R.j == 0) return q;
     const int k = R.k - s;
-    const dd T = {ldexp(PT_CR_EXP_T[R.j][0], k), ldexp(PT_CR_EXP_T[R.j][1], k)};
+    const dd T = {ldexp(PT_CR_EXPT(R.j, 0), k), ldexp(PT_CR_EXPT(R.j, 1), k)};
     const double one = ldexp(1.0, -s);
     const dd A = dd_add_d(T, -one);
     return dd_add(A, dd_mul(T, q));
+}
+
+// Accurate phase of expm1 (x in the main range).
+PT_CR_COLD double expm1_accurate(double x, unsigned* ambiguous) {
+    const ExpRed R = exp_reduce(x);
+    const int s = (R.k > 1000) ? 2 : 0;
+    const double back = s ? 4.0 : 1.0;
+    const dd a = expm1_combine(R, expm1_series_accurate(R.r), s);
+    double out;
+    if (round_test(a, kEpsAccurate, &out)) return out * back;
+    *ambiguous += 1u;
+    return (a.h + a.l) * back;
 }
 
 // Correctly rounded expm1(x).
@@ -268,10 +324,7 @@ PT_CR_HD double expm1_cr(double x, unsigned* ambiguous) {
     double out;
     const dd q = expm1_combine(R, expm1_series_quick(R.r), s);
     if (round_test(q, kEpsQuick, &out)) return out * back;
-    const dd a = expm1_combine(R, expm1_series_accurate(R.r), s);
-    if (round_test(a, kEpsAccurate, &out)) return out * back;
-    *ambiguous += 1u;
-    return (a.h + a.l) * back;
+    return expm1_accurate(x, ambiguous);
 }
 
 }  // namespace ptcr

@@ -99,6 +99,93 @@ __device__ __forceinline__ double adv64(double u1, double u2, double xi, double 
     return xn;
 }
 
+// Earliest exit over the three axes, FP64, with the same result as evaluating exit_time64 on
+// every axis and keeping the strictly smallest (ties to the lowest axis).  A cheap estimate
+// E of each axis' time is formed first (FP32 log1pf/logf, relative error below 5e-7); when
+// one axis is ahead of every other by more than 1e-5 relative, only its correctly rounded
+// time is evaluated -- the others cannot be smaller.  Otherwise (near ties, non-finite or
+// underflowing estimates) every axis is evaluated exactly.
+constexpr double kFilterMargin = 1e-5;
+
+__device__ __forceinline__ void select_exit64(const double (&u1)[3], const double (&u2)[3],
+                                              const double (&xi)[3], double& dt, int32_t& axis,
+                                              double& xe, unsigned& amb) {
+    double E[3];
+    bool unsure = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double A = u2[a] - u1[a];
+        const double up = u1[a] + A * xi[a];
+        double ue, e;
+        bool feasible;
+        if (up > 0.0) {
+            e = 1.0;
+            ue = u2[a];
+            feasible = ue > 0.0;
+        } else if (up < 0.0) {
+            e = 0.0;
+            ue = u1[a];
+            feasible = ue < 0.0;
+        } else {
+            e = 0.0;
+            ue = 0.0;
+            feasible = false;
+        }
+        double est = dinf();
+        if (feasible) {
+            const double r = (e - xi[a]) / up;
+            const double x = A * r;
+            if (x == 0.0) {
+                est = r;
+            } else if (x < -0.5) {
+                const float q = (float)(ue / up);
+                unsure = unsure || !(q >= 0x1p-126f);
+                est = (double)logf(q) / A;
+            } else {
+                const float xf = (float)x;
+                const float ph = (xf == 0.0f) ? 1.0f : log1pf(xf) / xf;
+                unsure = unsure || !__builtin_isfinite(ph);
+                est = r * (double)ph;
+            }
+            unsure = unsure || (est != est);
+        }
+        E[a] = est;
+    }
+    // candidate axis and its inputs (constant indices only: the arrays stay in registers)
+    int32_t w = -1;
+    double Ew = dinf(), w1 = 0.0, w2 = 0.0, wx = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (E[a] < Ew) {
+            Ew = E[a];
+            w = a;
+            w1 = u1[a];
+            w2 = u2[a];
+            wx = xi[a];
+        }
+    }
+    const double lim = Ew * (1.0 + kFilterMargin);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) unsure = unsure || (a != w && E[a] <= lim);
+    if (!unsure) {
+        if (w >= 0) {
+            dt = exit_time64(w1, w2, wx, xe, amb);
+            axis = w;
+        }
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double e = 0.0;
+        const double ta = exit_time64(u1[a], u2[a], xi[a], e, amb);
+        if (ta < dt) {
+            dt = ta;
+            axis = a;
+            xe = e;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 // One axis, mixed precision: FP32 velocities and local coordinate; FP64 for the
 // near-zero-gradient branch (|x| < 2^-10 or |A tau| < 2^-10) and for time.
@@ -193,12 +280,38 @@ struct Lane {
     double t;
     double s_next;      // time of snapshot ks (+inf past the last)
     R x[3];             // local coordinates
+    R v1[3], v2[3];     // packed layout: the current cell's face velocities (low, high face)
+    int32_t fl;         // packed layout: the current cell's flag word
 };
 
 template <bool BATCHED>
 __device__ __forceinline__ const GridDev& grid_of(const TrackParams& P, int32_t g) {
     if constexpr (BATCHED) return P.grids[g];
     else return P.g0;
+}
+
+// Gather one packed cell record: face velocities (with the direction sign) and the flag word.
+template <int PREC>
+__device__ __forceinline__ void load_rec(const GridDev& G, int32_t c, double sign,
+                                         typename Real<PREC>::T (&u1)[3],
+                                         typename Real<PREC>::T (&u2)[3], int32_t& fl) {
+    if constexpr (PREC == P64) {
+        const double2* r = reinterpret_cast<const double2*>(G.rec64 + c);
+        const double2 a = r[0], b = r[1], d = r[2];
+        fl = G.rec64[c].flags;
+        u1[0] = sign * a.x; u2[0] = sign * a.y;
+        u1[1] = sign * b.x; u2[1] = sign * b.y;
+        u1[2] = sign * d.x; u2[2] = sign * d.y;
+    } else {
+        const float4* r = reinterpret_cast<const float4*>(G.rec32 + c);
+        const float4 a = r[0];
+        const float4 b = r[1];
+        const float fs = (float)sign;
+        fl = __float_as_int(b.z);
+        u1[0] = fs * a.x; u2[0] = fs * a.y;
+        u1[1] = fs * a.z; u2[1] = fs * a.w;
+        u1[2] = fs * b.x; u2[2] = fs * b.y;
+    }
 }
 
 // Gather one cell: face velocities (with the direction sign) and the flag word.
@@ -344,6 +457,7 @@ __device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap
         }
         return ST_INVALID;
     }
+    if constexpr (LAYOUT == L_CELL) load_rec<PREC>(G, c, P.sign, L.v1, L.v2, L.fl);
     L.c = c;
     const int32_t plane = G.nx * G.ny;
     L.k = c / plane;
@@ -403,20 +517,33 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
     const GridDev& G = grid_of<BATCHED>(P, L.g);
     R u1[3], u2[3];
     int32_t fl;
-    load_cell<PREC, LAYOUT>(G, L, P.sign, u1, u2, fl);
+    if constexpr (LAYOUT == L_CELL) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            u1[a] = L.v1[a];
+            u2[a] = L.v2[a];
+        }
+        fl = L.fl;
+    } else {
+        load_cell<PREC, LAYOUT>(G, L, P.sign, u1, u2, fl);
+    }
 
     // earliest reachable face; exact ties go to the lowest axis
     double dt = dinf();
     int32_t axis = -1;
     R xe = 0;
+    if constexpr (PREC == P64) {
+        select_exit64(u1, u2, L.x, dt, axis, xe, L.amb);
+    } else {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        R e = 0;
-        const double ta = exit_time<PREC>(u1[a], u2[a], L.x[a], e, L.amb);
-        if (ta < dt) {
-            dt = ta;
-            axis = a;
-            xe = e;
+        for (int a = 0; a < 3; ++a) {
+            R e = 0;
+            const double ta = exit_time<PREC>(u1[a], u2[a], L.x[a], e, L.amb);
+            if (ta < dt) {
+                dt = ta;
+                axis = a;
+                xe = e;
+            }
         }
     }
 
@@ -434,6 +561,10 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
         L.t = P.t_max;
         return axis < 0 ? ST_STRANDED : ST_MAX_TIME;
     }
+
+    const int32_t hi = (xe == (R)1) ? 1 : 0;
+    const int32_t f = 2 * axis + hi;
+    const int32_t step = hi ? 1 : -1;
 
     // advance to the exit face: the two other axes move analytically
     if constexpr (TS) write_snaps<PREC>(L, G, u1, u2, P, snap, t_exit, false);
@@ -458,9 +589,6 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
     L.hash = (L.hash ^ (unsigned long long)(uint32_t)L.c) * kFnvPrime;
 
     // transfer to the neighbour across the exit face
-    const int32_t hi = (xe == (R)1) ? 1 : 0;
-    const int32_t f = 2 * axis + hi;
-    const int32_t step = hi ? 1 : -1;
     int32_t nfl_sink;
     if constexpr (LAYOUT == L_CELL) {
         if ((fl >> (NB_OUT + f)) & 1) return ST_BOUNDARY;
@@ -490,24 +618,32 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
     L.x[2] = (axis == 2) ? (R)1 - xe : L.x[2];
     if (nfl_sink && P.stop_at_sink) return ST_SINK;
     if ((int64_t)L.ncross >= P.max_steps) return ST_STEP_CAP;
+    // the particle continues: gather the new cell's record
+    if constexpr (LAYOUT == L_CELL) load_rec<PREC>(G, L.c, P.sign, L.v1, L.v2, L.fl);
     return 0;
 }
 
-// Block-level setup shared by both kernels: LDS snapshot copy and counters.
-struct BlockShared {
-    double snap[kMaxSnapLds];
+// Block-level setup shared by both kernels: LDS tables, snapshot times and counters.
+struct BlockCounters {
     unsigned int hist[8];
     unsigned long long cross;
     unsigned int amb;
 };
 
+template <bool TS> struct BlockShared;
+template <> struct BlockShared<false> : BlockCounters {};
+template <> struct BlockShared<true> : BlockCounters {
+    double snap[kMaxSnapLds];
+};
+
 template <bool TS>
-__device__ __forceinline__ const double* block_setup(BlockShared& S, const TrackParams& P) {
+__device__ __forceinline__ const double* block_setup(BlockShared<TS>& S, const TrackParams& P) {
     if (threadIdx.x < 8) S.hist[threadIdx.x] = 0u;
     if (threadIdx.x == 0) {
         S.cross = 0ull;
         S.amb = 0u;
     }
+    ptcr::lds_tables_init();
     const double* snap = P.snap_times;
     if constexpr (TS) {
         if (P.n_snap <= kMaxSnapLds) {
@@ -519,7 +655,7 @@ __device__ __forceinline__ const double* block_setup(BlockShared& S, const Track
     return snap;
 }
 
-__device__ __forceinline__ void block_flush(BlockShared& S, const TrackParams& P,
+__device__ __forceinline__ void block_flush(BlockCounters& S, const TrackParams& P,
                                             unsigned long long crossings, unsigned amb) {
     // wave-level reduction of the crossing count, one LDS atomic per wave
     for (int off = 32; off > 0; off >>= 1) crossings += __shfl_down(crossings, off, 64);
@@ -535,7 +671,7 @@ __device__ __forceinline__ void block_flush(BlockShared& S, const TrackParams& P
 // ---------------------------------------------------------------------------------------------
 template <int PREC, int LAYOUT, bool TS, bool BATCHED>
 __global__ void __launch_bounds__(kBlock) k_track_static(TrackParams P) {
-    __shared__ BlockShared S;
+    __shared__ BlockShared<TS> S;
     const double* snap = block_setup<TS>(S, P);
     unsigned long long crossings = 0;
     Lane<PREC> L;
@@ -551,7 +687,7 @@ __global__ void __launch_bounds__(kBlock) k_track_static(TrackParams P) {
 
 template <int PREC, int LAYOUT, bool TS, bool BATCHED>
 __global__ void __launch_bounds__(kBlock) k_track_persistent(TrackParams P) {
-    __shared__ BlockShared S;
+    __shared__ BlockShared<TS> S;
     const double* snap = block_setup<TS>(S, P);
     unsigned long long crossings = 0;
     const int lane = threadIdx.x & 63;
