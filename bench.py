@@ -174,6 +174,8 @@ def main():
     ap.add_argument("--only", action="store_true",
                     help="time only the primary variant (no other variants, no CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="first run one plain elementwise copy of this many bytes (HBM-counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -187,6 +189,14 @@ def main():
     from paper_2302_13590_amd import pt
     pt.load_library()
 
+    if args.copy_bytes > 0:
+        # a plain streaming kernel of known traffic: reads and writes copy_bytes each
+        n = args.copy_bytes // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.add(src, 0.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     log("building workload %s" % args.workload)
     t0 = time.perf_counter()
     w = workload(args.workload)

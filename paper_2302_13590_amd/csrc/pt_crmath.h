@@ -105,6 +105,13 @@ PT_CR_HD dd dd_add(dd x, dd y) {
     return fast_two_sum(v.h, t.l + v.l);
 }
 
+// x + y when no cancellation beyond a factor of a few can occur (the two high parts are
+// summed exactly, the low parts plainly): about half the operations of dd_add.
+PT_CR_HD dd dd_add_fast(dd x, dd y) {
+    const dd s = two_sum(x.h, y.h);
+    return fast_two_sum(s.h, s.l + (x.l + y.l));
+}
+
 PT_CR_HD dd dd_add_d(dd x, double d) {
     const dd s = two_sum(x.h, d);
     return fast_two_sum(s.h, s.l + x.l);
@@ -160,9 +167,36 @@ PT_CR_HD LogRed log_reduce(double yh, double yl) {
     const int j = (int)rint(m * 256.0);
     const double c = PT_CR_LOGC(j - PT_CR_LOG_J0);
     const dd p = two_prod(m, c);              // exact
-    dd r = fast_two_sum(p.h - 1.0, p.l);      // p.h - 1 is exact
+    // p.h - 1 is exact; ml*c is below 2^-52 |m c| and joins the low part
+    const dd r = fast_two_sum(p.h - 1.0, p.l + ml * c);
+    return {e, j, r};
+}
+
+// Same reduction with the correction term carried exactly (accurate phase).
+PT_CR_HD LogRed log_reduce_accurate(double yh, double yl) {
+    int e;
+    double m = frexp(yh, &e);
+    m *= 2.0;
+    e -= 1;
+    if (m > PT_CR_SQRT2) {
+        m *= 0.5;
+        e += 1;
+    }
+    const double ml = ldexp(yl, -e);
+    const int j = (int)rint(m * 256.0);
+    const double c = PT_CR_LOGC(j - PT_CR_LOG_J0);
+    const dd p = two_prod(m, c);
+    dd r = fast_two_sum(p.h - 1.0, p.l);
     r = dd_add(r, two_prod(ml, c));
     return {e, j, r};
+}
+
+PT_CR_HD dd log_sum_accurate(const LogRed& R, dd p) {
+    const double kd = (double)R.k;
+    dd kl = two_prod(kd, PT_CR_LN2_H);
+    kl.l = fma(kd, PT_CR_LN2_L, kl.l);
+    const dd L = {PT_CR_LOGL(R.j - PT_CR_LOG_J0, 0), PT_CR_LOGL(R.j - PT_CR_LOG_J0, 1)};
+    return dd_add(kl, dd_add(L, p));
 }
 
 PT_CR_HD dd log_sum(const LogRed& R, dd p) {
@@ -170,7 +204,9 @@ PT_CR_HD dd log_sum(const LogRed& R, dd p) {
     dd kl = two_prod(kd, PT_CR_LN2_H);
     kl.l = fma(kd, PT_CR_LN2_L, kl.l);
     const dd L = {PT_CR_LOGL(R.j - PT_CR_LOG_J0, 0), PT_CR_LOGL(R.j - PT_CR_LOG_J0, 1)};
-    return dd_add(kl, dd_add(L, p));
+    // |L + p| >= |p|/2 (L = ln(m_j), p = ln(m/m_j), same sign or |p| < |L|/2 within a bin),
+    // and k ln2 dominates L + p whenever k != 0
+    return dd_add_fast(kl, dd_add_fast(L, p));
 }
 
 // log1p(r) for |r| < 2^-8.4 with relative error < 2^-70.
@@ -188,7 +224,7 @@ PT_CR_HD dd log1p_series_quick(dd r) {
     S.l = fma(r.l, T, S.l);
     S = dd_add_d(S, -0.5);                            // -1/2 + r T
     const dd r2 = dd_mul(r, r);
-    return dd_add(r, dd_mul(r2, S));
+    return dd_add_fast(r, dd_mul(r2, S));             // |r^2 S| < |r| 2^-9
 }
 
 // log1p(r) for |r| < 2^-8.4 with relative error < 2^-100.
@@ -210,8 +246,8 @@ PT_CR_HD dd log1p_series_accurate(dd r) {
 
 // Accurate phase: it runs for about one evaluation in 2^15.
 PT_CR_COLD double log_accurate(double yh, double yl, unsigned* ambiguous) {
-    const LogRed R = log_reduce(yh, yl);
-    const dd a = log_sum(R, log1p_series_accurate(R.r));
+    const LogRed R = log_reduce_accurate(yh, yl);
+    const dd a = log_sum_accurate(R, log1p_series_accurate(R.r));
     double out;
     if (round_test(a, kEpsAccurate, &out)) return out;
     *ambiguous += 1u;
@@ -263,7 +299,7 @@ PT_CR_HD ExpRed exp_reduce(double x) {
     const double r0 = x - Kd * PT_CR_LN2_128_1;   // exact
     dd m = two_prod(Kd, PT_CR_LN2_128_2);
     m.l = fma(Kd, PT_CR_LN2_128_3, m.l);
-    const dd r = dd_add({r0, 0.0}, {-m.h, -m.l});
+    const dd r = dd_add_fast({r0, 0.0}, {-m.h, -m.l});
     return {K >> 7, K & 127, r};
 }
 
@@ -280,7 +316,7 @@ PT_CR_HD dd expm1_series_quick(dd r) {
     S.l = fma(r.l, U, S.l);
     S = dd_add_d(S, 0.5);                          // 1/2 + r U
     const dd r2 = dd_mul(r, r);
-    return dd_add(r, dd_mul(r2, S));
+    return dd_add_fast(r, dd_mul(r2, S));          // |r^2 S| < |r| 2^-9
 }
 
 // e^r - 1 for |r| <= ln2/256 with relative error < 2^-100.

@@ -100,12 +100,39 @@ __device__ __forceinline__ double adv64(double u1, double u2, double xi, double 
 }
 
 // Earliest exit over the three axes, FP64, with the same result as evaluating exit_time64 on
-// every axis and keeping the strictly smallest (ties to the lowest axis).  A cheap estimate
-// E of each axis' time is formed first (FP32 log1pf/logf, relative error below 5e-7); when
-// one axis is ahead of every other by more than 1e-5 relative, only its correctly rounded
-// time is evaluated -- the others cannot be smaller.  Otherwise (near ties, non-finite or
-// underflowing estimates) every axis is evaluated exactly.
-constexpr double kFilterMargin = 1e-5;
+// every axis and keeping the strictly smallest (ties to the lowest axis).  A cheap FP32
+// estimate E of each axis' time is formed first (relative error below 3e-6); when one axis
+// is ahead of every other by more than 2^-15 relative, only its correctly rounded time is
+// evaluated -- the others cannot be smaller.  Otherwise (near ties, estimates out of the FP32
+// range) every axis is evaluated exactly.
+constexpr double kFilterMargin = 0x1p-15;
+
+// FP32 estimate of (D/u_p) log1p(x)/x, x = A D/u_p, from the hardware reciprocal and base-2
+// logarithm (each within 1 ulp) and, for |x| < 1/8, the series of log1p(x)/x to x^7
+// (truncation below 7e-9).  `unsure` is raised when FP32 cannot bound it.
+__device__ __forceinline__ float exit_estimate(double D, double up, double A, double ue, bool& unsure) {
+    const float upf = (float)up;
+    const float rup = __builtin_amdgcn_rcpf(upf);
+    const float rf = (float)D * rup;
+    const float xf = (float)A * rf;
+    float ph;
+    if (fabsf(xf) < 0.125f) {
+        ph = fmaf(xf, -0.125f, 0.142857143f);
+        ph = fmaf(xf, ph, -0.166666667f);
+        ph = fmaf(xf, ph, 0.2f);
+        ph = fmaf(xf, ph, -0.25f);
+        ph = fmaf(xf, ph, 0.333333333f);
+        ph = fmaf(xf, ph, -0.5f);
+        ph = fmaf(xf, ph, 1.0f);
+    } else {
+        const float q = (xf > -0.5f) ? 1.0f + xf : (float)ue * rup;
+        unsure = unsure || !(q >= 0x1p-100f);
+        ph = (__builtin_amdgcn_logf(q) * 0.693147181f) * __builtin_amdgcn_rcpf(xf);
+    }
+    const float E = rf * ph;
+    unsure = unsure || !(fabsf(upf) >= 0x1p-100f && fabsf(upf) <= 0x1p100f) || !__builtin_isfinite(E);
+    return E;
+}
 
 __device__ __forceinline__ void select_exit64(const double (&u1)[3], const double (&u2)[3],
                                               const double (&xi)[3], double& dt, int32_t& axis,
@@ -132,23 +159,7 @@ __device__ __forceinline__ void select_exit64(const double (&u1)[3], const doubl
             feasible = false;
         }
         double est = dinf();
-        if (feasible) {
-            const double r = (e - xi[a]) / up;
-            const double x = A * r;
-            if (x == 0.0) {
-                est = r;
-            } else if (x < -0.5) {
-                const float q = (float)(ue / up);
-                unsure = unsure || !(q >= 0x1p-126f);
-                est = (double)logf(q) / A;
-            } else {
-                const float xf = (float)x;
-                const float ph = (xf == 0.0f) ? 1.0f : log1pf(xf) / xf;
-                unsure = unsure || !__builtin_isfinite(ph);
-                est = r * (double)ph;
-            }
-            unsure = unsure || (est != est);
-        }
+        if (feasible) est = (double)exit_estimate(e - xi[a], up, A, ue, unsure);
         E[a] = est;
     }
     // candidate axis and its inputs (constant indices only: the arrays stay in registers)

@@ -26,7 +26,8 @@ extern "C" void ptcr_phases(int fn, const double* x, double* qh, double* ql, dou
             const ptcr::dd y = fn == 0 ? ptcr::two_sum(1.0, x[i]) : ptcr::dd{x[i], 0.0};
             const ptcr::LogRed R = ptcr::log_reduce(y.h, y.l);
             q = ptcr::log_sum(R, ptcr::log1p_series_quick(R.r));
-            a = ptcr::log_sum(R, ptcr::log1p_series_accurate(R.r));
+            const ptcr::LogRed RA = ptcr::log_reduce_accurate(y.h, y.l);
+            a = ptcr::log_sum_accurate(RA, ptcr::log1p_series_accurate(RA.r));
         }
         qh[i] = q.h; ql[i] = q.l; ah[i] = a.h; al[i] = a.l;
     }
