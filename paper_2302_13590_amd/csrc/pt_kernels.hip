@@ -198,11 +198,37 @@ __device__ __forceinline__ void select_exit64(const double (&u1)[3], const doubl
 }
 
 // ---------------------------------------------------------------------------------------------
-// One axis, mixed precision: FP32 velocities and local coordinate; FP64 for the
-// near-zero-gradient branch (|x| < 2^-10 or |A tau| < 2^-10) and for time.
+// One axis, mixed precision: FP32 velocities, local coordinate and in-cell arithmetic, with
+// the hardware reciprocal, base-2 logarithm and exponential (1 ulp each) and short series
+// near zero; FP64 for time and for the near-zero-gradient branch (|x| < 2^-10 or
+// |A tau| < 2^-10), where the series are evaluated in double.
 constexpr float kNearZero = 0x1p-10f;
+constexpr float kLn2f = 0.693147181f;
+constexpr float kLog2ef = 1.44269504f;
+
+// log1p(x)/x for |x| < 1/8, series to x^7 (truncation below 7e-9)
+__device__ __forceinline__ float log1p_over_x_series(float x) {
+    float p = fmaf(x, -0.125f, 0.142857143f);
+    p = fmaf(x, p, -0.166666667f);
+    p = fmaf(x, p, 0.2f);
+    p = fmaf(x, p, -0.25f);
+    p = fmaf(x, p, 0.333333333f);
+    p = fmaf(x, p, -0.5f);
+    return fmaf(x, p, 1.0f);
+}
+
+// expm1(y)/y for |y| < 1/8, series to y^6 (truncation below 3e-11)
+__device__ __forceinline__ float expm1_over_y_series(float y) {
+    float p = fmaf(y, 1.98412698e-4f, 1.38888889e-3f);
+    p = fmaf(y, p, 8.33333333e-3f);
+    p = fmaf(y, p, 4.16666667e-2f);
+    p = fmaf(y, p, 0.166666667f);
+    p = fmaf(y, p, 0.5f);
+    return fmaf(y, p, 1.0f);
+}
 
 __device__ __forceinline__ double exit_time_mix(float u1, float u2, float xi, float& xe, unsigned& amb) {
+    (void)amb;
     const float A = u2 - u1;
     const float up = u1 + A * xi;
     float ue;
@@ -218,25 +244,30 @@ __device__ __forceinline__ double exit_time_mix(float u1, float u2, float xi, fl
         return dinf();
     }
     const float D = xe - xi;
-    const float r = D / up;
+    const float rup = __builtin_amdgcn_rcpf(up);
+    const float r = D * rup;
     const float x = A * r;
     if (fabsf(x) < kNearZero) {
+        // log1p(x)/x = 1 - x/2 + x^2/3 - x^3/4 + x^4/5 - ..., truncation below 2^-52 here
         const double rd = (double)D / (double)up;
         const double xd = (double)A * rd;
-        double dt = (xd == 0.0) ? rd : rd * (ptcr::log1p_cr(xd, &amb) / xd);
-        return dt < 0.0 ? 0.0 : dt;
+        const double ph = 1.0 + xd * (-0.5 + xd * (1.0 / 3.0 + xd * (-0.25 + 0.2 * xd)));
+        return rd * ph;
     }
-    float dt;
-    if (x < -0.5f) {
-        dt = logf(ue / up) / A;
+    float ph;
+    if (fabsf(x) < 0.125f) {
+        ph = log1p_over_x_series(x);
     } else {
-        dt = r * (log1pf(x) / x);
+        const float q = (x > -0.5f) ? 1.0f + x : ue * rup;   // q = u_e/u_p
+        ph = (__builtin_amdgcn_logf(q) * kLn2f) * __builtin_amdgcn_rcpf(x);
     }
+    float dt = r * ph;
     if (dt < 0.0f) dt = 0.0f;
     return (double)dt;
 }
 
 __device__ __forceinline__ float adv_mix(float u1, float u2, float xi, double tau, unsigned& amb) {
+    (void)amb;
     const float A = u2 - u1;
     const float up = u1 + A * xi;
     if (up == 0.0f) return xi;
@@ -244,11 +275,15 @@ __device__ __forceinline__ float adv_mix(float u1, float u2, float xi, double ta
     const float y = A * tf;
     float xn;
     if (fabsf(y) < kNearZero) {
+        // expm1(y)/y = 1 + y/2 + y^2/6 + y^3/24 + y^4/120 + ..., truncation below 2^-59 here
         const double yd = (double)A * tau;
-        const double psi = (yd == 0.0) ? 1.0 : ptcr::expm1_cr(yd, &amb) / yd;
+        const double psi = 1.0 + yd * (0.5 + yd * (1.0 / 6.0 + yd * (1.0 / 24.0 + yd * (1.0 / 120.0))));
         xn = (float)((double)xi + ((double)up * tau) * psi);
     } else {
-        xn = xi + (up * tf) * (expm1f(y) / y);
+        float ps;
+        if (fabsf(y) < 0.125f) ps = expm1_over_y_series(y);
+        else ps = (__builtin_amdgcn_exp2f(y * kLog2ef) - 1.0f) * __builtin_amdgcn_rcpf(y);
+        xn = xi + (up * tf) * ps;
     }
     xn = (xn < 0.0f) ? 0.0f : xn;
     xn = (xn > 1.0f) ? 1.0f : xn;
