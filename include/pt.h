@@ -163,9 +163,11 @@ typedef struct {
                                    * same arguments come again)                                 */
     int32_t block;                /* threads per block, 0 = default; multiple of 64, <= 1024      */
     int32_t blocks_per_cu;        /* persistent grid size per compute unit, 0 = default          */
-    int32_t refill;               /* persistent: refill a wave when at least this many lanes     *
-                                   * are idle, 1..64, 0 = default                               */
-    int32_t steps_per_refill;     /* persistent: crossings per lane between refill checks, 0 = d. */
+    int32_t refill;               /* persistent: refill a wave's idle lanes once at least this    *
+                                   * many are idle, 1..64, 0 = default (1)                      */
+    int32_t steps_per_refill;     /* persistent: crossings per lane between refill points, 0 = 1 */
+    int32_t chunk;                /* persistent: particles a wave claims from the device queue  *
+                                   * per atomic, >= 1, 0 = default (64)                          */
 } pt_track_opts;
 
 /* Fill *o with the defaults: endpoint, FP64, auto schedule and layout, forward,

@@ -1,0 +1,138 @@
+"""Autotuner of the tracking launch: schedule, block size, refill threshold, chunk size.
+
+The paper's scheduling study (Results, "Thread scheduling") shows that the best
+distribution of particles over workers depends on the workload: static
+scheduling suits uniform particles, dynamic scheduling adapts to slow ones.  On
+the GPU the same choice appears as the static kernel against the persistent
+work-queue kernel, plus its launch parameters.  This module times candidate
+launches of one workload through the C ABI (device-event kernel time, median of
+repeats) and records the fastest in a JSON cache keyed by device, workload,
+precision and mode, which the benchmark and applications read back.
+
+    python -m paper_2302_13590_amd.autotune --workload C2 --precision fp64
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import statistics
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuning.json")
+
+
+def candidates(quick: bool = False):
+    """Launch parameter sets to try (dicts of pt_track_opts fields)."""
+    out = [dict(schedule=1, block=b) for b in (64, 128, 256)]
+    refills = (1, 8, 16, 32) if not quick else (8, 32)
+    chunks = (32, 128, 512) if not quick else (128,)
+    for b, r, c, s in itertools.product((128, 256), refills, chunks, (1, 2)):
+        out.append(dict(schedule=2, block=b, refill=r, chunk=c, steps_per_refill=s))
+    return out
+
+
+def key(device: str, workload: str, precision: str, mode: str) -> str:
+    return "|".join((device, workload, precision, mode))
+
+
+def load_cache(path: str = CACHE) -> dict:
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def lookup(k: str, path: str = CACHE):
+    """Tuned launch parameters for key k, or None."""
+    e = load_cache(path).get(k)
+    return None if e is None else dict(e["params"])
+
+
+def save(k: str, entry: dict, path: str = CACHE):
+    cache = load_cache(path)
+    cache[k] = entry
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+        f.write("\n")
+    os.replace(tmp, path)
+
+
+def tune(run_once, cands, reps: int = 3, log=None):
+    """run_once(params) -> kernel ms.  Returns (best params, [(params, median ms)])."""
+    table = []
+    for params in cands:
+        run_once(params)                       # warm-up (graph build, caches)
+        ms = statistics.median(run_once(params) for _ in range(reps))
+        table.append((params, ms))
+        if log:
+            log("%-70s %.3f ms" % (params, ms))
+    best = min(table, key=lambda t: t[1])
+    return best[0], table
+
+
+def device_name() -> str:
+    import torch
+    return torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--out", default=CACHE)
+    args = ap.parse_args(argv)
+
+    root = os.path.dirname(HERE)
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import torch
+    from paper_2302_13590_amd import pt
+    from workloads import configs as C
+
+    w = C.CONFIGS[args.workload]()
+    grids = [pt.pt_load_grid(g) for g in w.grids]
+    pristine = pt.DeviceParticles.from_numpy(w.particles, "cuda")
+    work = pristine.clone()
+    n = pristine.n
+    out_xyz = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    base = dict(precision=pt.PT_MIXED if args.precision == "mixed" else pt.PT_FP64,
+                layout=pt.PT_LAYOUT_CELL, use_graph=1, out_xyz=out_xyz, t_max=w.t_max)
+    mode = "endpoint"
+    if w.snap_times is not None:
+        snap = torch.empty((n, len(w.snap_times), 3), dtype=torch.float64, device="cuda")
+        base.update(mode=pt.PT_TIMESERIES, snap_times=w.snap_times, snap_xyz=snap)
+        mode = "timeseries"
+    ref = None
+
+    def run_once(params):
+        nonlocal ref
+        work.copy_(pristine)
+        s = pt.track(grids, work, group_offsets=w.group_offsets, group_grid=w.group_grid,
+                     **dict(base, **params))
+        if ref is None:
+            ref = s["crossings"]
+        assert s["crossings"] == ref, "launch parameters changed the result"
+        return s["kernel_ms"]
+
+    t0 = time.time()
+    best, table = tune(run_once, candidates(args.quick), args.reps,
+                       log=lambda m: print(m, file=sys.stderr, flush=True))
+    k = key(device_name(), args.workload, args.precision, mode)
+    ms = min(t[1] for t in table)
+    entry = {"params": best, "kernel_ms": ms, "crossings": ref, "candidates": len(table),
+             "crossings_per_s": ref / (ms * 1e-3), "tuned_s": round(time.time() - t0, 1)}
+    save(k, entry, args.out)
+    print(json.dumps({"key": k, **entry}), flush=True)
+    for g in grids:
+        g.release()
+
+
+if __name__ == "__main__":
+    main()

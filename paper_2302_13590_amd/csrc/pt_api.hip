@@ -405,8 +405,8 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
         return fail(PT_ERR_INVALID_ARG, "block must be 0 or a multiple of 64 in [64, 1024]");
     if (o->block > 256) return fail(PT_ERR_UNSUPPORTED, "block > 256 exceeds the kernels' launch bounds");
     if (o->refill < 0 || o->refill > 64) return fail(PT_ERR_INVALID_ARG, "refill must be in [0, 64]");
-    if (o->steps_per_refill < 0 || o->blocks_per_cu < 0)
-        return fail(PT_ERR_INVALID_ARG, "steps_per_refill and blocks_per_cu must be >= 0");
+    if (o->steps_per_refill < 0 || o->blocks_per_cu < 0 || o->chunk < 0)
+        return fail(PT_ERR_INVALID_ARG, "steps_per_refill, blocks_per_cu and chunk must be >= 0");
     if (o->precision == PT_MIXED && o->layout == PT_LAYOUT_FACES)
         return fail(PT_ERR_UNSUPPORTED, "mixed precision needs the packed cell layout");
     const bool ts = o->mode == PT_TIMESERIES;
@@ -542,8 +542,9 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     P.snap_xyz = ts ? o->snap_xyz : nullptr;
     P.out_xyz = o->out_xyz;
     P.counters = r->d_counters;
-    P.refill = o->refill ? o->refill : 32;
+    P.refill = o->refill ? o->refill : 1;
     P.steps_per_refill = o->steps_per_refill ? o->steps_per_refill : 1;
+    P.chunk = o->chunk ? o->chunk : 64;
 
     hipError_t e = hipEventRecord(r->ev0, s);
     if (e == hipSuccess) {

@@ -91,6 +91,8 @@ struct TrackParams {
     Counters* counters;
     int32_t refill;
     int32_t steps_per_refill;
+    int32_t chunk;
+    int32_t pad_chunk;
 };
 
 enum Precision { P64 = 0, PMIX = 1 };

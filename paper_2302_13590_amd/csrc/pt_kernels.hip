@@ -736,28 +736,42 @@ __global__ void __launch_bounds__(kBlock) k_track_persistent(TrackParams P) {
     __shared__ BlockShared<TS> S;
     const double* snap = block_setup<TS>(S, P);
     unsigned long long crossings = 0;
-    const int lane = threadIdx.x & 63;
     const unsigned long long n = (unsigned long long)P.n;
     const int refill = P.refill;
     const int steps = P.steps_per_refill;
-    bool exhausted = false;  // wave-uniform
+    const unsigned long long chunk = (unsigned long long)P.chunk;
+    // Wave-uniform state: the wave's current chunk [cnext, cend) of queue slots, claimed with one
+    // atomic; idle lanes are refilled from it at every refill point.
+    unsigned long long cnext = 0, cend = 0;
+    bool exhausted = false;  // the device queue is empty
     Lane<PREC> L;
     L.amb = 0u;
     L.pid = -1;
     for (;;) {
         const unsigned long long idle = __ballot(L.pid < 0);
         const int nidle = __popcll(idle);
-        if (!exhausted && nidle >= refill) {
-            unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(&P.counters->queue, (unsigned long long)nidle);
-            base = __shfl(base, 0, 64);
-            if (base + (unsigned long long)nidle >= n) exhausted = true;
+        const unsigned long long avail = cend - cnext;
+        if (nidle > 0 && (nidle >= refill || nidle == 64) && (avail > 0 || !exhausted)) {
+            unsigned long long nbase = 0, nlen = 0;
+            if (avail < (unsigned long long)nidle && !exhausted) {
+                unsigned long long base = 0;
+                if ((threadIdx.x & 63) == 0) base = atomicAdd(&P.counters->queue, chunk);
+                base = __shfl(base, 0, 64);
+                if (base < n) {
+                    nbase = base;
+                    nlen = (n - base < chunk) ? n - base : chunk;
+                }
+                if (base + chunk >= n) exhausted = true;
+            }
             if (L.pid < 0) {
-                const unsigned long long slot =
-                    base + __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
-                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
-                if (slot < n) {
-                    L.pid = (int64_t)slot;
+                const unsigned long long rank =
+                    __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
+                                              __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+                long long slot = -1;
+                if (rank < avail) slot = (long long)(cnext + rank);
+                else if (rank - avail < nlen) slot = (long long)(nbase + (rank - avail));
+                if (slot >= 0) {
+                    L.pid = slot;
                     const int32_t st = begin<PREC, LAYOUT, TS, BATCHED>(L, P, snap);
                     if (st != 0) {
                         if (st > 0) finish<PREC, TS, BATCHED>(L, st, P, S.hist);
@@ -765,9 +779,16 @@ __global__ void __launch_bounds__(kBlock) k_track_persistent(TrackParams P) {
                     }
                 }
             }
+            if (avail >= (unsigned long long)nidle) {
+                cnext += (unsigned long long)nidle;
+            } else {
+                const unsigned long long used = (unsigned long long)nidle - avail;
+                cnext = nbase + (used < nlen ? used : nlen);
+                cend = nbase + nlen;
+            }
         }
         if (__ballot(L.pid >= 0) == 0ull) {
-            if (exhausted) break;
+            if (exhausted && cnext >= cend) break;
             continue;
         }
         for (int s = 0; s < steps; ++s) {

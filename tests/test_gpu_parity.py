@@ -153,6 +153,8 @@ def test_schedules_and_shapes_bit_identical(pt):
     ref = gpu_track([g], p, schedule=1, layout=2)
     for kw in (dict(schedule=2), dict(schedule=2, block=64), dict(schedule=2, block=128, refill=1),
                dict(schedule=2, refill=64, steps_per_refill=4), dict(schedule=2, blocks_per_cu=1),
+               dict(schedule=2, chunk=1), dict(schedule=2, chunk=1000, refill=16),
+               dict(schedule=2, chunk=7, steps_per_refill=3, block=192),
                dict(schedule=2, use_graph=1), dict(schedule=1, layout=1), dict(schedule=1, block=64)):
         out = gpu_track([g], p, **kw)
         for k in ("status", "cell", "ncross", "path_hash", "xi", "eta", "zeta", "t", "out_xyz"):
