@@ -95,10 +95,10 @@ class Case:
             self.snap = torch.empty((n, len(w.snap_times), 3), dtype=torch.float64, device="cuda")
         self.stream = torch.cuda.current_stream()
 
-    def opts(self, precision, schedule, **kw):
+    def opts(self, precision, schedule_name, **kw):
         pt = self.pt
         o = dict(precision=pt.PT_MIXED if precision == "mixed" else pt.PT_FP64,
-                 schedule=pt.PT_SCHED_STATIC if schedule == "static" else pt.PT_SCHED_PERSISTENT,
+                 schedule=pt.PT_SCHED_STATIC if schedule_name == "static" else pt.PT_SCHED_PERSISTENT,
                  layout=pt.PT_LAYOUT_CELL, use_graph=1, out_xyz=self.out_xyz, t_max=self.w.t_max)
         if self.snap is not None:
             o.update(mode=pt.PT_TIMESERIES, snap_times=self.w.snap_times, snap_xyz=self.snap)
@@ -134,13 +134,60 @@ class Case:
             g.release()
 
 
-def roofline(res, n, precision):
+KERNEL_SOURCES = ["paper_2302_13590_amd/csrc/pt_kernels.hip", "paper_2302_13590_amd/csrc/pt_crmath.h",
+                  "paper_2302_13590_amd/csrc/pt_crtables.h", "paper_2302_13590_amd/csrc/pt_internal.h"]
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
+
+def kernel_sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload, precision, schedule):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel sources for this workload and launch; else None."""
+    path = os.path.join(ROOT, "profiles", "track_%s_%s_%s_counters.txt" % (precision, workload, schedule))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_sources_sha256") != kernel_sources_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def kernel_name(precision, schedule, timeseries=False, batched=False):
+    return "k_track_%s<%s, cell, %s%s>" % ("static" if schedule == "static" else "persistent",
+                                           "FP64" if precision == "fp64" else "mixed",
+                                           "timeseries" if timeseries else "endpoint",
+                                           ", batched" if batched else "")
+
+
+def roofline(res, n, precision, workload, schedule, timeseries=False, batched=False):
     bytes_launch = res["crossings_per_step"] * BYTES_PER_CROSSING[precision] + n * BYTES_PER_PARTICLE
     achieved = bytes_launch / (res["kernel_ms"] * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": profiled_traffic(workload, precision, schedule),
             "bytes_per_launch": int(bytes_launch), "kernel_ms": round(res["kernel_ms"], 4),
-            "kernel": "k_track_persistent<%s, cell, endpoint>" % ("FP64" if precision == "fp64" else "mixed")}
+            "kernel": kernel_name(precision, schedule, timeseries, batched)}
+
+
+def tuned_params(workload, precision, mode):
+    from paper_2302_13590_amd import autotune
+    return autotune.lookup(autotune.key(autotune.device_name(), workload, precision, mode))
 
 
 def cpu_baseline(w, n_threads):
@@ -170,7 +217,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="C2", choices=sorted(DESCR))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--schedule", default="persistent", choices=["persistent", "static"])
+    ap.add_argument("--schedule", default="auto", choices=["auto", "persistent", "static"],
+                    help="auto: the autotuned launch for this workload (tuning.json)")
     ap.add_argument("--only", action="store_true",
                     help="time only the primary variant (no other variants, no CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -201,22 +249,40 @@ def main():
     t0 = time.perf_counter()
     w = workload(args.workload)
     n = w.particles.n
+    mode = "timeseries" if w.snap_times is not None else "endpoint"
+    batched = len(w.grids) > 1
     log("inputs ready in %.1fs: %d particles, %d grid(s)" % (time.perf_counter() - t0, n, len(w.grids)))
     case = Case(w)
-    primary = case.time(case.opts(args.precision, args.schedule), args.steps, args.warmup)
-    log("primary %s/%s: %.4g crossings/s, %.3f ms/step, kernel %.3f ms" % (
-        args.precision, args.schedule, primary["value"], primary["ms_per_step"], primary["kernel_ms"]))
+
+    def launch(precision, schedule):
+        """Launch parameters: the autotuned ones when they use this schedule, else defaults."""
+        tuned = tuned_params(args.workload, precision, mode) or {}
+        sched_id = 1 if schedule == "static" else 2
+        if schedule == "auto" and tuned:
+            return tuned, ("static" if tuned.get("schedule") == 1 else "persistent")
+        if schedule == "auto":
+            return dict(schedule=2), "persistent"
+        if tuned.get("schedule") == sched_id:
+            return tuned, schedule
+        return dict(schedule=sched_id), schedule
+
+    params, sched = launch(args.precision, args.schedule)
+    primary = case.time(case.opts(args.precision, sched, **params), args.steps, args.warmup)
+    log("primary %s/%s %s: %.4g crossings/s, %.3f ms/step, kernel %.3f ms" % (
+        args.precision, sched, params, primary["value"], primary["ms_per_step"], primary["kernel_ms"]))
     variants = {}
     if not args.only:
-        for prec, sched in (("fp64", "static"), ("fp64", "persistent"), ("mixed", "persistent")):
-            if (prec, sched) == (args.precision, args.schedule):
+        for prec, sc in (("fp64", "static"), ("fp64", "persistent"), ("mixed", "auto")):
+            p2, s2 = launch(prec, sc)
+            if (prec, s2) == (args.precision, sched):
                 continue
-            r = case.time(case.opts(prec, sched), args.steps, args.warmup)
-            variants["%s_%s" % (prec, sched)] = dict(
+            r = case.time(case.opts(prec, s2, **p2), args.steps, args.warmup)
+            variants["%s_%s" % (prec, s2)] = dict(
                 value=r["value"], ms_per_step=round(r["ms_per_step"], 4),
                 kernel_ms=round(r["kernel_ms"], 4), crossings_per_step=r["crossings_per_step"],
-                roofline_frac=roofline(r, n, prec)["frac"])
-            log("variant %s/%s: %.4g crossings/s" % (prec, sched, r["value"]))
+                launch=p2, roofline_frac=roofline(r, n, prec, args.workload, s2, mode == "timeseries",
+                                                  batched)["frac"])
+            log("variant %s/%s: %.4g crossings/s" % (prec, s2, r["value"]))
     case.release()
 
     out = {
@@ -234,13 +300,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": DESCR[args.workload], "particles": n,
                    "crossings_per_step": primary["crossings_per_step"], "precision": args.precision,
-                   "schedule": args.schedule, "layout": "cell", "launch": "hipGraph",
+                   "schedule": sched, "layout": "cell", "launch": "hipGraph", "params": params,
                    "block": primary["summary"]["block"], "grid": primary["summary"]["grid"]},
-        "roofline": roofline(primary, n, args.precision),
+        "roofline": roofline(primary, n, args.precision, args.workload, sched, mode == "timeseries",
+                             batched),
     }
     if variants:
         out["variants"] = variants
-    if not args.only and not args.no_cpu_baseline and len(w.grids) == 1:
+    if not args.only and not args.no_cpu_baseline and not batched:
         cores = len(os.sched_getaffinity(0))
         threads = min(cores, 16)
         log("timing the CPU oracle on %d threads" % threads)

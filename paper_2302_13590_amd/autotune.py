@@ -76,8 +76,13 @@ def tune(run_once, cands, reps: int = 3, log=None):
 
 
 def device_name() -> str:
+    """Tuning key of the current device: architecture and compute-unit count (e.g. gfx950/256cu)."""
     import torch
-    return torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
+    if not torch.cuda.is_available():
+        return "none"
+    prop = torch.cuda.get_device_properties(0)
+    arch = getattr(prop, "gcnArchName", "") or torch.cuda.get_device_name(0)
+    return "%s/%dcu" % (arch.split(":")[0], prop.multi_processor_count)
 
 
 def main(argv=None):
