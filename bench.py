@@ -196,7 +196,7 @@ def cpu_baseline(w, n_threads):
     p = w.particles
     res = {}
     # all host cores, dynamic scheduling of the particle loop (the paper's best protocol)
-    m = min(p.n, 1_000_000)
+    m = min(p.n, 500_000)
     sub = p.subset(slice(0, m))
     t0 = time.perf_counter()
     r = O.track(w.grids[0], sub, t_max=w.t_max, threads=n_threads)

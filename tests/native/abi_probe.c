@@ -1,0 +1,34 @@
+/* Prints sizeof and field offsets of the structs in include/pt.h, for the ABI test. */
+#include <stddef.h>
+#include <stdio.h>
+
+#include "pt.h"
+
+#define F(T, f) printf("%s.%s %zu\n", #T, #f, offsetof(T, f))
+#define S(T) printf("%s.sizeof %zu\n", #T, sizeof(T))
+
+int main(void) {
+    S(pt_grid_desc);
+    F(pt_grid_desc, nx); F(pt_grid_desc, ny); F(pt_grid_desc, nz); F(pt_grid_desc, dx);
+    F(pt_grid_desc, dy); F(pt_grid_desc, dz); F(pt_grid_desc, x0); F(pt_grid_desc, y0);
+    F(pt_grid_desc, z0); F(pt_grid_desc, qx); F(pt_grid_desc, qy); F(pt_grid_desc, qz);
+    F(pt_grid_desc, porosity); F(pt_grid_desc, porosity_scalar); F(pt_grid_desc, flags);
+    F(pt_grid_desc, mem); F(pt_grid_desc, balance_tol);
+    S(pt_particles);
+    F(pt_particles, n); F(pt_particles, cell); F(pt_particles, xi); F(pt_particles, eta);
+    F(pt_particles, zeta); F(pt_particles, t); F(pt_particles, status); F(pt_particles, ncross);
+    F(pt_particles, path_hash); F(pt_particles, n_groups); F(pt_particles, group_offsets);
+    F(pt_particles, group_grid);
+    S(pt_track_opts);
+    F(pt_track_opts, mode); F(pt_track_opts, precision); F(pt_track_opts, schedule);
+    F(pt_track_opts, layout); F(pt_track_opts, direction); F(pt_track_opts, stop_at_sink);
+    F(pt_track_opts, t_max); F(pt_track_opts, max_steps); F(pt_track_opts, snap_times);
+    F(pt_track_opts, n_snap); F(pt_track_opts, snap_xyz); F(pt_track_opts, out_xyz);
+    F(pt_track_opts, use_graph); F(pt_track_opts, block); F(pt_track_opts, blocks_per_cu);
+    F(pt_track_opts, refill); F(pt_track_opts, steps_per_refill); F(pt_track_opts, chunk);
+    S(pt_summary);
+    F(pt_summary, crossings); F(pt_summary, n_tracked); F(pt_summary, status_count);
+    F(pt_summary, kernel_ms); F(pt_summary, schedule); F(pt_summary, layout); F(pt_summary, block);
+    F(pt_summary, grid); F(pt_summary, cr_ambiguous);
+    return 0;
+}
