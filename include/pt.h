@@ -82,6 +82,10 @@ extern "C" {
 #define PT_SCHED_PERSISTENT 2  /* resident waves pull particles from a device work queue and   *
                                 * refill finished lanes (wave-level compaction)               */
 
+#define PT_SORT_AUTO 0         /* order the work by starting cell when n >= 65536              */
+#define PT_SORT_NONE 1         /* process particles in index order                            */
+#define PT_SORT_CELL 2         /* order the work by starting cell (counting sort on device)   */
+
 #define PT_LAYOUT_AUTO 0
 #define PT_LAYOUT_FACES 1      /* face-flow arrays + porosity + flags; velocities per step    */
 #define PT_LAYOUT_CELL 2       /* one packed record of six face velocities + flags per cell   */
@@ -119,7 +123,7 @@ int pt_load_grid(const pt_grid_desc* desc, void* hip_stream, pt_grid** out);
 
 /* ---- particles -------------------------------------------------------------------------- */
 typedef struct {
-    int64_t n;                    /* number of particles, >= 0 (0 is a valid empty run)          */
+    int64_t n;                    /* number of particles, 0 <= n < 2^31 (0: an empty run)         */
     int32_t* cell;                /* [n] linear cell id                      device, in/out      */
     double* xi;                   /* [n] local coordinates in [0,1]          device, in/out      */
     double* eta;
@@ -168,6 +172,8 @@ typedef struct {
     int32_t steps_per_refill;     /* persistent: crossings per lane between refill points, 0 = 1 */
     int32_t chunk;                /* persistent: particles a wave claims from the device queue  *
                                    * per atomic, >= 1, 0 = default (64)                          */
+    int32_t sort;                 /* PT_SORT_*: processing order (never changes a result); the   *
+                                   * ordered work is split into one contiguous part per die     */
 } pt_track_opts;
 
 /* Fill *o with the defaults: endpoint, FP64, auto schedule and layout, forward,

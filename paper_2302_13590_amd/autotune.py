@@ -27,11 +27,12 @@ CACHE = os.path.join(HERE, "tuning.json")
 
 def candidates(quick: bool = False):
     """Launch parameter sets to try (dicts of pt_track_opts fields)."""
-    out = [dict(schedule=1, block=b) for b in (64, 128, 256)]
-    refills = (1, 8, 16, 32) if not quick else (8, 32)
-    chunks = (32, 128, 512) if not quick else (128,)
-    for b, r, c, s in itertools.product((128, 256), refills, chunks, (1, 2)):
-        out.append(dict(schedule=2, block=b, refill=r, chunk=c, steps_per_refill=s))
+    sorts = (1, 2)                      # index order, or ordered by starting cell
+    out = [dict(schedule=1, block=b, sort=o) for b in (64, 128, 256) for o in sorts]
+    refills = (1, 8, 16) if not quick else (8,)
+    chunks = (32, 128) if not quick else (32,)
+    for b, r, c, s, o in itertools.product((128, 256), refills, chunks, (1, 2), sorts):
+        out.append(dict(schedule=2, block=b, refill=r, chunk=c, steps_per_refill=s, sort=o))
     return out
 
 

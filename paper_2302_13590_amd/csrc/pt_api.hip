@@ -116,6 +116,8 @@ struct pt_run {
     // per-run device tables (batched runs, snapshot times) and their pinned staging
     void* d_tables = nullptr;
     size_t d_tables_bytes = 0;
+    void* d_sort = nullptr;             // processing order [n] + bucket histogram
+    size_t d_sort_bytes = 0;
     void* h_tables = nullptr;
     size_t h_tables_bytes = 0;
     // cached graph: [reset counters, track] for one exact set of kernel arguments
@@ -138,6 +140,7 @@ void destroy_run(pt_run* r) {
     if (r->h_counters) (void)hipHostFree(r->h_counters);
     if (r->d_tables) (void)hipFree(r->d_tables);
     if (r->h_tables) (void)hipHostFree(r->h_tables);
+    if (r->d_sort) (void)hipFree(r->d_sort);
     delete r;
 }
 
@@ -190,6 +193,23 @@ int ensure_tables(pt_run* r, size_t bytes) {
 }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int ensure_sort(pt_run* r, size_t bytes) {
+    if (bytes <= r->d_sort_bytes) return PT_OK;
+    if (r->d_sort) (void)hipFree(r->d_sort);
+    r->d_sort = nullptr;
+    r->d_sort_bytes = 0;
+    HIP_TRY(hipMalloc(&r->d_sort, bytes));
+    r->d_sort_bytes = bytes;
+    return PT_OK;
+}
+
+// One kernel launch of a run: launched eagerly in order, or as a chain of graph nodes.
+struct Launch {
+    const void* fn;
+    dim3 grid, block;
+    void* arg;
+};
 
 // ---------------------------------------------------------------------------------------------
 // grid validation of host-resident inputs (device-resident inputs are checked by k_build)
@@ -388,6 +408,7 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
             return fail(PT_ERR_BAD_HANDLE, "grids[%d] is not a live grid handle", q);
     if (!p || !o) return fail(PT_ERR_INVALID_ARG, "particles and options must not be NULL");
     if (p->n < 0) return fail(PT_ERR_INVALID_ARG, "n must be >= 0");
+    if (p->n >= (int64_t(1) << 31)) return fail(PT_ERR_UNSUPPORTED, "at most 2^31 - 1 particles per call");
     if (p->n > 0 && (!p->cell || !p->xi || !p->eta || !p->zeta || !p->t || !p->status || !p->ncross ||
                      !p->path_hash))
         return fail(PT_ERR_INVALID_ARG, "a particle state array is NULL");
@@ -405,6 +426,7 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
         return fail(PT_ERR_INVALID_ARG, "block must be 0 or a multiple of 64 in [64, 1024]");
     if (o->block > 256) return fail(PT_ERR_UNSUPPORTED, "block > 256 exceeds the kernels' launch bounds");
     if (o->refill < 0 || o->refill > 64) return fail(PT_ERR_INVALID_ARG, "refill must be in [0, 64]");
+    if (o->sort < PT_SORT_AUTO || o->sort > PT_SORT_CELL) return fail(PT_ERR_INVALID_ARG, "bad sort");
     if (o->steps_per_refill < 0 || o->blocks_per_cu < 0 || o->chunk < 0)
         return fail(PT_ERR_INVALID_ARG, "steps_per_refill, blocks_per_cu and chunk must be >= 0");
     if (o->precision == PT_MIXED && o->layout == PT_LAYOUT_FACES)
@@ -459,7 +481,9 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     const int block = o->block ? o->block : 256;
     int grid;
     if (key.sched == S_STATIC) {
-        grid = (int)std::max<int64_t>(1, (p->n + block - 1) / block);
+        // a multiple of the die count: die d takes the d-th eighth of the slots
+        const int64_t nb = std::max<int64_t>(1, (p->n + block - 1) / block);
+        grid = (int)((nb + kXcd - 1) / kXcd * kXcd);
     } else {
         int per_cu = o->blocks_per_cu;
         if (!per_cu) {
@@ -484,7 +508,9 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     const size_t b_offs = batched ? align_up(sizeof(int64_t) * (n_groups + 1), 256) : 0;
     const size_t b_gg = batched ? align_up(sizeof(int32_t) * n_groups, 256) : 0;
     const size_t b_snap = ts ? align_up(sizeof(double) * o->n_snap, 256) : 0;
-    const size_t total = b_grids + b_offs + b_gg + b_snap;
+    const bool sort = o->sort == PT_SORT_CELL || (o->sort == PT_SORT_AUTO && p->n >= (1 << 16));
+    const size_t b_base = (sort && batched) ? align_up(sizeof(int64_t) * n_grids, 256) : 0;
+    const size_t total = b_grids + b_offs + b_gg + b_snap + b_base;
     TrackParams P;
     std::memset(&P, 0, sizeof P);
     if (total) {
@@ -514,6 +540,15 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
             std::memcpy(h + off, o->snap_times, sizeof(double) * o->n_snap);
             P.snap_times = reinterpret_cast<const double*>(dd + off);
             off += b_snap;
+        }
+        if (b_base) {
+            int64_t* base = reinterpret_cast<int64_t*>(h + off);
+            int64_t acc = 0;
+            for (int32_t q = 0; q < n_grids; ++q) {
+                base[q] = acc;
+                acc += (int64_t)grids[q]->gd.nx * grids[q]->gd.ny * grids[q]->gd.nz;
+            }
+            off += b_base;
         }
         hipError_t e = hipMemcpyAsync(r->d_tables, r->h_tables, total, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) {
@@ -546,15 +581,66 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     P.steps_per_refill = o->steps_per_refill ? o->steps_per_refill : 1;
     P.chunk = o->chunk ? o->chunk : 64;
 
+    // spatial ordering of the particles (counting sort by starting cell)
+    SortParams SP;
+    std::memset(&SP, 0, sizeof SP);
+    if (sort) {
+        int64_t cells = 0;
+        for (int32_t q = 0; q < (batched ? n_grids : 1); ++q)
+            cells += (int64_t)grids[q]->gd.nx * grids[q]->gd.ny * grids[q]->gd.nz;
+        int shift = 0;
+        while ((cells >> shift) >= kMaxBuckets) ++shift;
+        SP.nbuckets = (int32_t)(cells >> shift) + 1;
+        SP.shift = shift;
+        const size_t b_order = align_up(sizeof(int32_t) * (size_t)p->n, 256);
+        rc = ensure_sort(r, b_order + sizeof(unsigned) * (size_t)SP.nbuckets);
+        if (rc != PT_OK) {
+            destroy_run(r);
+            return rc;
+        }
+        SP.n = p->n;
+        SP.cell = p->cell;
+        SP.status = p->status;
+        SP.n_groups = batched ? n_groups : 0;
+        SP.group_offsets = P.group_offsets;
+        SP.group_grid = P.group_grid;
+        SP.grid_base = batched ? reinterpret_cast<const int64_t*>(static_cast<unsigned char*>(r->d_tables) +
+                                                                  (total - b_base))
+                               : nullptr;
+        SP.order = static_cast<int32_t*>(r->d_sort);
+        SP.hist = reinterpret_cast<unsigned*>(static_cast<unsigned char*>(r->d_sort) + b_order);
+        P.order = SP.order;
+    }
+    Counters* cptr = r->d_counters;
+    std::vector<Launch> seq;
+    seq.push_back({reset_kernel(), dim3(1), dim3(64), &cptr});
+    if (p->n > 0) {
+        if (sort) {
+            const unsigned nb = (unsigned)((p->n + 255) / 256);
+            seq.push_back({sort_clear_kernel(), dim3(std::min(256u, (unsigned)(SP.nbuckets + 255) / 256)),
+                           dim3(256), &SP});
+            seq.push_back({sort_hist_kernel(), dim3(nb), dim3(256), &SP});
+            seq.push_back({sort_scan_kernel(), dim3(1), dim3(1024), &SP});
+            seq.push_back({sort_scatter_kernel(), dim3(nb), dim3(256), &SP});
+        }
+        seq.push_back({fn, dim3(grid), dim3(block), &P});
+    }
+
     hipError_t e = hipEventRecord(r->ev0, s);
     if (e == hipSuccess) {
         if (o->use_graph) {
-            std::vector<unsigned char> gkey(sizeof P + sizeof(const void*) + 2 * sizeof(int));
-            unsigned char* kp = gkey.data();
-            std::memcpy(kp, &P, sizeof P);
-            std::memcpy(kp + sizeof P, &fn, sizeof fn);
-            std::memcpy(kp + sizeof P + sizeof fn, &grid, sizeof grid);
-            std::memcpy(kp + sizeof P + sizeof fn + sizeof grid, &block, sizeof block);
+            // key: every launch's function, shape and argument bytes
+            std::vector<unsigned char> gkey;
+            for (const Launch& L : seq) {
+                const size_t bytes = (L.arg == &P) ? sizeof P : (L.arg == &SP) ? sizeof SP : sizeof cptr;
+                const unsigned char* a = static_cast<const unsigned char*>(L.arg);
+                const unsigned char* f = reinterpret_cast<const unsigned char*>(&L.fn);
+                gkey.insert(gkey.end(), f, f + sizeof L.fn);
+                const unsigned dims[2] = {L.grid.x, L.block.x};
+                const unsigned char* d = reinterpret_cast<const unsigned char*>(dims);
+                gkey.insert(gkey.end(), d, d + sizeof dims);
+                gkey.insert(gkey.end(), a, a + bytes);
+            }
             if (!r->exec || r->graph_key != gkey) {
                 if (r->exec) {
                     (void)hipGraphExecDestroy(r->exec);
@@ -563,25 +649,20 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
                     r->graph = nullptr;
                 }
                 hipGraph_t gr = nullptr;
-                hipGraphNode_t n_reset = nullptr, n_track = nullptr;
-                Counters* cptr = r->d_counters;
-                void* reset_args[] = {&cptr};
-                void* track_args[] = {&P};
-                hipKernelNodeParams kr;
-                std::memset(&kr, 0, sizeof kr);
-                kr.func = const_cast<void*>(reset_kernel());
-                kr.gridDim = dim3(1);
-                kr.blockDim = dim3(64);
-                kr.kernelParams = reset_args;
-                hipKernelNodeParams kt;
-                std::memset(&kt, 0, sizeof kt);
-                kt.func = const_cast<void*>(fn);
-                kt.gridDim = dim3(grid);
-                kt.blockDim = dim3(block);
-                kt.kernelParams = track_args;
                 e = hipGraphCreate(&gr, 0);
-                if (e == hipSuccess) e = hipGraphAddKernelNode(&n_reset, gr, nullptr, 0, &kr);
-                if (e == hipSuccess && p->n > 0) e = hipGraphAddKernelNode(&n_track, gr, &n_reset, 1, &kt);
+                hipGraphNode_t prev = nullptr;
+                for (size_t q = 0; e == hipSuccess && q < seq.size(); ++q) {
+                    void* args[] = {seq[q].arg};
+                    hipKernelNodeParams kp;
+                    std::memset(&kp, 0, sizeof kp);
+                    kp.func = const_cast<void*>(seq[q].fn);
+                    kp.gridDim = seq[q].grid;
+                    kp.blockDim = seq[q].block;
+                    kp.kernelParams = args;
+                    hipGraphNode_t node = nullptr;
+                    e = hipGraphAddKernelNode(&node, gr, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+                    prev = node;
+                }
                 if (e == hipSuccess) e = hipGraphInstantiate(&r->exec, gr, nullptr, nullptr, 0);
                 if (e == hipSuccess) {
                     r->graph = gr;
@@ -593,9 +674,8 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
             }
             if (e == hipSuccess) e = hipGraphLaunch(r->exec, s);
         } else {
-            Counters* cptr = r->d_counters;
-            e = launch(reset_kernel(), dim3(1), dim3(64), &cptr, s);
-            if (e == hipSuccess && p->n > 0) e = launch(fn, dim3(grid), dim3(block), &P, s);
+            for (size_t q = 0; e == hipSuccess && q < seq.size(); ++q)
+                e = launch(seq[q].fn, seq[q].grid, seq[q].block, seq[q].arg, s);
         }
     }
     if (e == hipSuccess) e = hipEventRecord(r->ev1, s);

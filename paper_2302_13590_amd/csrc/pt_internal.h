@@ -54,14 +54,17 @@ struct GridDev {
     int32_t nx, ny, nz, pad;
 };
 
-// Counter block of a run (device), cleared by the reset kernel.
+constexpr int kXcd = 8;   // accelerator complex dies; workgroup b runs on die b mod 8
+
+// Counters of a run (device), cleared by the reset kernel.
 struct Counters {
     unsigned long long crossings;
     unsigned long long status[8];
-    unsigned long long queue;       // next particle index handed out by the work queue
     unsigned long long cr_ambiguous;  // correctly rounded evaluations left undecided
-    unsigned long long pad[5];
+    unsigned long long queue[kXcd];   // next slot handed out in each die's segment
+    unsigned long long pad[14];
 };
+static_assert(sizeof(Counters) == 32 * 8, "Counters is 32 words");
 
 struct TrackParams {
     int64_t n;
@@ -93,7 +96,28 @@ struct TrackParams {
     int32_t steps_per_refill;
     int32_t chunk;
     int32_t pad_chunk;
+    // Processing order: slot s of the work holds particle order[s] (nullptr: s itself).  Slots
+    // are split into kXcd contiguous segments, one per die, so that a die's L2 sees one
+    // spatially coherent part of the particles.
+    const int32_t* order;
 };
+
+// Spatial ordering of particles by starting cell (counting sort into buckets of cells).
+struct SortParams {
+    int64_t n;
+    const int32_t* cell;
+    const int32_t* status;
+    const int64_t* group_offsets;   // batched runs: group table and the first global cell id
+    const int32_t* group_grid;      //   of each grid
+    const int64_t* grid_base;
+    int32_t n_groups;
+    int32_t shift;                  // bucket = global cell id >> shift
+    int32_t nbuckets;
+    int32_t pad;
+    unsigned* hist;                 // [nbuckets]
+    int32_t* order;                 // [n]
+};
+constexpr int kMaxBuckets = 1 << 16;
 
 enum Precision { P64 = 0, PMIX = 1 };
 enum Layout { L_FACES = 1, L_CELL = 2 };
@@ -106,6 +130,10 @@ struct KernelKey {
 // Kernel lookup (defined in pt_kernels.hip).
 const void* track_kernel(const KernelKey& k);
 const void* reset_kernel();
+const void* sort_clear_kernel();
+const void* sort_hist_kernel();
+const void* sort_scan_kernel();
+const void* sort_scatter_kernel();
 const void* build_kernel();
 const void* check_kernel();
 

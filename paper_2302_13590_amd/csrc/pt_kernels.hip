@@ -722,8 +722,13 @@ __global__ void __launch_bounds__(kBlock) k_track_static(TrackParams P) {
     unsigned long long crossings = 0;
     Lane<PREC> L;
     L.amb = 0u;
-    L.pid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (L.pid < P.n) {
+    // die d = blockIdx.x mod 8 takes the d-th contiguous eighth of the slots (gridDim.x is a
+    // multiple of 8)
+    const int64_t per_die = (int64_t)gridDim.x / kXcd;
+    const int64_t blk = (int64_t)(blockIdx.x % kXcd) * per_die + blockIdx.x / kXcd;
+    const int64_t slot = blk * blockDim.x + threadIdx.x;
+    if (slot < P.n) {
+        L.pid = P.order ? (int64_t)P.order[slot] : slot;
         int32_t st = begin<PREC, LAYOUT, TS, BATCHED>(L, P, snap);
         while (st == 0) st = track_step<PREC, LAYOUT, TS, BATCHED>(L, P, snap, crossings);
         if (st > 0) finish<PREC, TS, BATCHED>(L, st, P, S.hist);
@@ -743,7 +748,12 @@ __global__ void __launch_bounds__(kBlock) k_track_persistent(TrackParams P) {
     // Wave-uniform state: the wave's current chunk [cnext, cend) of queue slots, claimed with one
     // atomic; idle lanes are refilled from it at every refill point.
     unsigned long long cnext = 0, cend = 0;
-    bool exhausted = false;  // the device queue is empty
+    bool exhausted = false;  // every die's segment is empty
+    // The slots are split into kXcd segments; a wave first drains its own die's segment
+    // (L2 locality), then the following ones.
+    const unsigned long long seg = (n + kXcd - 1) / kXcd;
+    const int die = blockIdx.x % kXcd;
+    int tried = 0;           // segments found empty so far (wave-uniform)
     Lane<PREC> L;
     L.amb = 0u;
     L.pid = -1;
@@ -753,15 +763,21 @@ __global__ void __launch_bounds__(kBlock) k_track_persistent(TrackParams P) {
         const unsigned long long avail = cend - cnext;
         if (nidle > 0 && (nidle >= refill || nidle == 64) && (avail > 0 || !exhausted)) {
             unsigned long long nbase = 0, nlen = 0;
-            if (avail < (unsigned long long)nidle && !exhausted) {
+            while (avail < (unsigned long long)nidle && !exhausted && nlen == 0) {
+                const int sg = (die + tried) % kXcd;
+                const unsigned long long lo = (unsigned long long)sg * seg;
+                const unsigned long long hi = (lo + seg < n) ? lo + seg : n;
                 unsigned long long base = 0;
-                if ((threadIdx.x & 63) == 0) base = atomicAdd(&P.counters->queue, chunk);
-                base = __shfl(base, 0, 64);
-                if (base < n) {
+                if ((threadIdx.x & 63) == 0) base = atomicAdd(&P.counters->queue[sg], chunk);
+                base = lo + __shfl(base, 0, 64);
+                if (base < hi) {
                     nbase = base;
-                    nlen = (n - base < chunk) ? n - base : chunk;
+                    nlen = (hi - base < chunk) ? hi - base : chunk;
                 }
-                if (base + chunk >= n) exhausted = true;
+                if (base + chunk >= hi) {
+                    ++tried;
+                    if (tried == kXcd) exhausted = true;
+                }
             }
             if (L.pid < 0) {
                 const unsigned long long rank =
@@ -771,7 +787,7 @@ __global__ void __launch_bounds__(kBlock) k_track_persistent(TrackParams P) {
                 if (rank < avail) slot = (long long)(cnext + rank);
                 else if (rank - avail < nlen) slot = (long long)(nbase + (rank - avail));
                 if (slot >= 0) {
-                    L.pid = slot;
+                    L.pid = P.order ? (int64_t)P.order[slot] : slot;
                     const int32_t st = begin<PREC, LAYOUT, TS, BATCHED>(L, P, snap);
                     if (st != 0) {
                         if (st > 0) finish<PREC, TS, BATCHED>(L, st, P, S.hist);
@@ -808,6 +824,71 @@ __global__ void k_reset(Counters* c) {
     unsigned long long* w = reinterpret_cast<unsigned long long*>(c);
     const int n = sizeof(Counters) / sizeof(unsigned long long);
     if ((int)threadIdx.x < n) w[threadIdx.x] = 0ull;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Spatial ordering: counting sort of the particles by the bucket of their starting cell.  The
+// order only changes which lanes and dies process which particles, never a result.
+
+__device__ __forceinline__ uint32_t sort_bucket(const SortParams& S, int64_t p) {
+    const int32_t c = S.cell[p];
+    const int32_t st = S.status[p];
+    if (c < 0 || (st != ST_ACTIVE && st != ST_MAX_TIME)) return 0u;
+    int64_t key = c;
+    if (S.n_groups > 0) {
+        int32_t lo = 0, hi = S.n_groups;
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (S.group_offsets[mid] <= p) lo = mid;
+            else hi = mid;
+        }
+        key += S.grid_base[S.group_grid[lo]];
+    }
+    const int64_t b = key >> S.shift;
+    return (uint32_t)(b < S.nbuckets ? b : S.nbuckets - 1);
+}
+
+__global__ void __launch_bounds__(256) k_sort_clear(SortParams S) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < S.nbuckets;
+         q += (int64_t)gridDim.x * blockDim.x)
+        S.hist[q] = 0u;
+}
+
+__global__ void __launch_bounds__(256) k_sort_hist(SortParams S) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < S.n) atomicAdd(&S.hist[sort_bucket(S, p)], 1u);
+}
+
+// Exclusive prefix sum of the histogram in place, one workgroup of 1024 threads.
+__global__ void __launch_bounds__(1024) k_sort_scan(SortParams S) {
+    __shared__ unsigned part[1024];
+    const int per = (S.nbuckets + 1023) / 1024;
+    const int lo = threadIdx.x * per;
+    const int hi = (lo + per < S.nbuckets) ? lo + per : S.nbuckets;
+    unsigned sum = 0;
+    for (int q = lo; q < hi; ++q) sum += S.hist[q];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const unsigned v = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    unsigned run = part[threadIdx.x] - sum;
+    for (int q = lo; q < hi; ++q) {
+        const unsigned h = S.hist[q];
+        S.hist[q] = run;
+        run += h;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_sort_scatter(SortParams S) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < S.n) {
+        const unsigned pos = atomicAdd(&S.hist[sort_bucket(S, p)], 1u);
+        S.order[pos] = (int32_t)p;
+    }
 }
 
 // Grid load: validate the field and build both packed records of every cell.
@@ -894,6 +975,10 @@ const void* track_kernel(const KernelKey& k) {
 }
 
 const void* reset_kernel() { return reinterpret_cast<const void*>(&k_reset); }
+const void* sort_clear_kernel() { return reinterpret_cast<const void*>(&k_sort_clear); }
+const void* sort_hist_kernel() { return reinterpret_cast<const void*>(&k_sort_hist); }
+const void* sort_scan_kernel() { return reinterpret_cast<const void*>(&k_sort_scan); }
+const void* sort_scatter_kernel() { return reinterpret_cast<const void*>(&k_sort_scatter); }
 const void* build_kernel() { return reinterpret_cast<const void*>(&k_build); }
 
 }  // namespace pt

@@ -28,6 +28,7 @@ PT_ENDPOINT, PT_TIMESERIES = 0, 1
 PT_FP64, PT_MIXED = 0, 1
 PT_SCHED_AUTO, PT_SCHED_STATIC, PT_SCHED_PERSISTENT = 0, 1, 2
 PT_LAYOUT_AUTO, PT_LAYOUT_FACES, PT_LAYOUT_CELL = 0, 1, 2
+PT_SORT_AUTO, PT_SORT_NONE, PT_SORT_CELL = 0, 1, 2
 FNV_OFFSET = 0xCBF29CE484222325
 
 _p = ctypes.c_void_p
@@ -56,7 +57,7 @@ class pt_track_opts(ctypes.Structure):
                 ("snap_xyz", _p), ("out_xyz", _p), ("use_graph", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("refill", ctypes.c_int32), ("steps_per_refill", ctypes.c_int32),
-                ("chunk", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("sort", ctypes.c_int32)]
 
 
 class pt_summary(ctypes.Structure):
@@ -243,7 +244,7 @@ def pt_default_opts() -> pt_track_opts:
 def make_opts(mode=PT_ENDPOINT, precision=PT_FP64, schedule=PT_SCHED_AUTO, layout=PT_LAYOUT_AUTO,
               direction=1, stop_at_sink=1, t_max=math.inf, max_steps=1 << 20, snap_times=None,
               snap_xyz=None, out_xyz=None, use_graph=0, block=0, blocks_per_cu=0, refill=0,
-              steps_per_refill=0, chunk=0):
+              steps_per_refill=0, chunk=0, sort=0):
     o = pt_default_opts()
     o.mode, o.precision, o.schedule, o.layout = mode, precision, schedule, layout
     o.direction, o.stop_at_sink, o.t_max, o.max_steps = direction, stop_at_sink, t_max, max_steps
@@ -255,8 +256,8 @@ def make_opts(mode=PT_ENDPOINT, precision=PT_FP64, schedule=PT_SCHED_AUTO, layou
         o.n_snap = st.shape[0]
     o.snap_xyz = _ptr(snap_xyz)
     o.out_xyz = _ptr(out_xyz)
-    o.use_graph, o.block, o.blocks_per_cu, o.refill, o.steps_per_refill, o.chunk = (
-        use_graph, block, blocks_per_cu, refill, steps_per_refill, chunk)
+    o.use_graph, o.block, o.blocks_per_cu, o.refill, o.steps_per_refill, o.chunk, o.sort = (
+        use_graph, block, blocks_per_cu, refill, steps_per_refill, chunk, sort)
     o._keep = keep
     return o
 

@@ -26,6 +26,7 @@ int main(void) {
     F(pt_track_opts, n_snap); F(pt_track_opts, snap_xyz); F(pt_track_opts, out_xyz);
     F(pt_track_opts, use_graph); F(pt_track_opts, block); F(pt_track_opts, blocks_per_cu);
     F(pt_track_opts, refill); F(pt_track_opts, steps_per_refill); F(pt_track_opts, chunk);
+    F(pt_track_opts, sort);
     S(pt_summary);
     F(pt_summary, crossings); F(pt_summary, n_tracked); F(pt_summary, status_count);
     F(pt_summary, kernel_ms); F(pt_summary, schedule); F(pt_summary, layout); F(pt_summary, block);

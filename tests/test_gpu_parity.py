@@ -85,8 +85,9 @@ def test_batched_groups(pt):
     p = C.concat(parts)
     r = O.track_groups(grids, p, offs, gg)
     for sched in (1, 2):
-        out = gpu_track(grids, p, group_offsets=offs, group_grid=gg, schedule=sched)
-        compare(out, r, label="batched sched %d" % sched, spacing=(10.0, 10.0, 2.0))
+        for sort in (1, 2):
+            out = gpu_track(grids, p, group_offsets=offs, group_grid=gg, schedule=sched, sort=sort)
+            compare(out, r, label="batched sched %d sort %d" % (sched, sort), spacing=(10.0, 10.0, 2.0))
     snaps = np.logspace(-1, 3, 20)
     r = O.track_groups(grids, p, offs, gg, snap_times=snaps, t_max=300.0)
     out = gpu_track(grids, p, group_offsets=offs, group_grid=gg, snap_times=snaps, t_max=300.0)
@@ -155,6 +156,8 @@ def test_schedules_and_shapes_bit_identical(pt):
                dict(schedule=2, refill=64, steps_per_refill=4), dict(schedule=2, blocks_per_cu=1),
                dict(schedule=2, chunk=1), dict(schedule=2, chunk=1000, refill=16),
                dict(schedule=2, chunk=7, steps_per_refill=3, block=192),
+               dict(schedule=2, sort=2), dict(schedule=1, sort=2), dict(schedule=2, sort=2, chunk=1),
+               dict(schedule=2, sort=2, use_graph=1),
                dict(schedule=2, use_graph=1), dict(schedule=1, layout=1), dict(schedule=1, block=64)):
         out = gpu_track([g], p, **kw)
         for k in ("status", "cell", "ncross", "path_hash", "xi", "eta", "zeta", "t", "out_xyz"):
