@@ -209,7 +209,12 @@ PT_CR_HD dd log_sum(const LogRed& R, dd p) {
     return dd_add_fast(kl, dd_add_fast(L, p));
 }
 
-// log1p(r) for |r| < 2^-8.4 with relative error < 2^-70.
+// log1p(r) for r = x + l (|r| < 2^-8.4, |l| <= ulp(x)/2), as a double-double with relative
+// error below 2^-69.5:
+//   log1p(r) = x - x^2/2 + x^3 T(x) + l (1 - x + x^2) + O(2^-100 |r|),
+//   T = 1/3 - x/4 + ... - x^7/10 (truncation below 2^-83 |r|).
+// x^2 = p + pe exactly, x - p/2 is summed exactly; the remaining terms are below
+// 2^-18.5 |r| and are evaluated in double.
 PT_CR_HD dd log1p_series_quick(dd r) {
     const double x = r.h;
     double T = -0x1.999999999999ap-4;                 // -1/10
@@ -220,11 +225,12 @@ PT_CR_HD dd log1p_series_quick(dd r) {
     T = fma(x, T, 0x1.999999999999ap-3);              //  1/5
     T = fma(x, T, -0x1.0000000000000p-2);             // -1/4
     T = fma(x, T, 0x1.5555555555555p-2);              //  1/3
-    dd S = two_prod(x, T);
-    S.l = fma(r.l, T, S.l);
-    S = dd_add_d(S, -0.5);                            // -1/2 + r T
-    const dd r2 = dd_mul(r, r);
-    return dd_add_fast(r, dd_mul(r2, S));             // |r^2 S| < |r| 2^-9
+    const double p = x * x;
+    const double pe = fma(x, x, -p);
+    const double h = -0.5 * p;                        // exact
+    const double lo = fma(r.l, p - x, r.l) + fma(p * x, T, -0.5 * pe);
+    const dd s = fast_two_sum(x, h);                  // |h| < |x| 2^-9.4
+    return fast_two_sum(s.h, s.l + lo);
 }
 
 // log1p(r) for |r| < 2^-8.4 with relative error < 2^-100.
@@ -262,26 +268,44 @@ PT_CR_HD double log_dd_cr(double yh, double yl, unsigned* ambiguous) {
     return log_accurate(yh, yl, ambiguous);
 }
 
+// Inputs of log1p that need no reduction: stores the result and returns true.
+PT_CR_HD bool log1p_special(double x, double* out) {
+    if (!(x > -1.0)) {
+        *out = (x == -1.0) ? -__builtin_huge_val() : __builtin_nan("");   // x < -1 or NaN
+        return true;
+    }
+    if (fabs(x) < 0x1p-60 || x == __builtin_huge_val()) {
+        *out = x;                       // log1p(x) = x (1 - x/2 + ...) rounds to x
+        return true;
+    }
+    return false;
+}
+
+// Inputs of log that need no reduction: stores the result and returns true.
+PT_CR_HD bool log_special(double x, double* out) {
+    if (!(x > 0.0)) {
+        *out = (x == 0.0) ? -__builtin_huge_val() : __builtin_nan("");
+        return true;
+    }
+    if (x == __builtin_huge_val() || x == 1.0) {
+        *out = (x == 1.0) ? 0.0 : x;
+        return true;
+    }
+    return false;
+}
+
 // Correctly rounded log1p(x).
 PT_CR_HD double log1p_cr(double x, unsigned* ambiguous) {
-    if (!(x > -1.0)) {
-        if (x == -1.0) return -__builtin_huge_val();
-        return __builtin_nan("");       // x < -1 or NaN
-    }
-    if (fabs(x) < 0x1p-60) return x;    // log1p(x) = x (1 - x/2 + ...) rounds to x
-    if (x == __builtin_huge_val()) return x;
+    double out;
+    if (log1p_special(x, &out)) return out;
     const dd y = two_sum(1.0, x);       // 1 + x exactly
     return log_dd_cr(y.h, y.l, ambiguous);
 }
 
 // Correctly rounded log(x).
 PT_CR_HD double log_cr(double x, unsigned* ambiguous) {
-    if (!(x > 0.0)) {
-        if (x == 0.0) return -__builtin_huge_val();
-        return __builtin_nan("");
-    }
-    if (x == __builtin_huge_val()) return x;
-    if (x == 1.0) return 0.0;
+    double out;
+    if (log_special(x, &out)) return out;
     return log_dd_cr(x, 0.0, ambiguous);
 }
 
@@ -303,7 +327,12 @@ PT_CR_HD ExpRed exp_reduce(double x) {
     return {K >> 7, K & 127, r};
 }
 
-// e^r - 1 for |r| <= ln2/256 with relative error < 2^-70.
+// e^r - 1 for r = x + l (|r| <= ln2/256, |l| <= ulp(x)/2), as a double-double with relative
+// error below 2^-70:
+//   e^r - 1 = x + x^2/2 + x^3 U(x) + l (1 + x + x^2/2) + O(2^-100 |r|),
+//   U = 1/3! + x/4! + ... + x^5/8! (truncation below 2^-88 |r|).
+// x^2 = p + pe exactly, x + p/2 is summed exactly; the remaining terms are below
+// 2^-19.6 |r| and are evaluated in double.
 PT_CR_HD dd expm1_series_quick(dd r) {
     const double x = r.h;
     double U = 0x1.a01a01a01a01ap-16;              // 1/8!
@@ -312,11 +341,12 @@ PT_CR_HD dd expm1_series_quick(dd r) {
     U = fma(x, U, 0x1.1111111111111p-7);           // 1/5!
     U = fma(x, U, 0x1.5555555555555p-5);           // 1/4!
     U = fma(x, U, 0x1.5555555555555p-3);           // 1/3!
-    dd S = two_prod(x, U);
-    S.l = fma(r.l, U, S.l);
-    S = dd_add_d(S, 0.5);                          // 1/2 + r U
-    const dd r2 = dd_mul(r, r);
-    return dd_add_fast(r, dd_mul(r2, S));          // |r^2 S| < |r| 2^-9
+    const double p = x * x;
+    const double pe = fma(x, x, -p);
+    const double h = 0.5 * p;                      // exact
+    const double lo = fma(r.l, x + h, r.l) + fma(p * x, U, 0.5 * pe);
+    const dd s = fast_two_sum(x, h);               // |h| < |x| 2^-9.5
+    return fast_two_sum(s.h, s.l + lo);
 }
 
 // e^r - 1 for |r| <= ln2/256 with relative error < 2^-100.
@@ -326,13 +356,18 @@ PT_CR_HD dd expm1_series_accurate(dd r) {
     return dd_mul(r, S);
 }
 
-// (2^k T_j - 1) + 2^k T_j q, scaled by 2^-s (s > 0 only near overflow).
+// (2^k T_j - 1) + 2^k T_j q, scaled by 2^-s (s > 0 only near overflow).  When (k, j) is not
+// (0, 0), |x - r| >= ln2/128 and |2^k T_j q| < 0.502 |2^k T_j - 1| (worst at x - r = ln2/128,
+// r = -ln2/256), so the sum cancels by about a factor of 2 at most: the quick phase adds
+// the low parts plainly (dd_add_fast, error below 2^-100 relative).
+template <bool FAST>
 PT_CR_HD dd expm1_combine(const ExpRed& R, dd q, int s) {
     if (R.k == 0 && R.j == 0) return q;
     const int k = R.k - s;
     const dd T = {ldexp(PT_CR_EXPT(R.j, 0), k), ldexp(PT_CR_EXPT(R.j, 1), k)};
     const double one = ldexp(1.0, -s);
     const dd A = dd_add_d(T, -one);
+    if (FAST) return dd_add_fast(A, dd_mul(T, q));
     return dd_add(A, dd_mul(T, q));
 }
 
@@ -341,7 +376,7 @@ PT_CR_COLD double expm1_accurate(double x, unsigned* ambiguous) {
     const ExpRed R = exp_reduce(x);
     const int s = (R.k > 1000) ? 2 : 0;
     const double back = s ? 4.0 : 1.0;
-    const dd a = expm1_combine(R, expm1_series_accurate(R.r), s);
+    const dd a = expm1_combine<false>(R, expm1_series_accurate(R.r), s);
     double out;
     if (round_test(a, kEpsAccurate, &out)) return out * back;
     *ambiguous += 1u;
@@ -358,7 +393,7 @@ PT_CR_HD double expm1_cr(double x, unsigned* ambiguous) {
     const int s = (R.k > 1000) ? 2 : 0;  // keep 2^k finite; the final scaling by 4 is exact
     const double back = s ? 4.0 : 1.0;
     double out;
-    const dd q = expm1_combine(R, expm1_series_quick(R.r), s);
+    const dd q = expm1_combine<true>(R, expm1_series_quick(R.r), s);
     if (round_test(q, kEpsQuick, &out)) return out * back;
     return expm1_accurate(x, ambiguous);
 }

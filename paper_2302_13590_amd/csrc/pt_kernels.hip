@@ -74,13 +74,28 @@ __device__ __forceinline__ double exit_time64(double u1, double u2, double xi, d
     const double D = xe - xi;
     const double r = D / up;
     const double x = A * r;
-    double dt;
-    if (x == 0.0) {
-        dt = r;
-    } else if (x < -0.5) {
-        dt = ptcr::log_cr(ue / up, &amb) / A;
-    } else {
-        dt = r * (ptcr::log1p_cr(x, &amb) / x);
+    double dt = r;
+    if (x != 0.0) {
+        // One logarithm site for both forms, so a wave whose lanes take different forms
+        // runs the correctly rounded logarithm once: log(u_e/u_p) when x < -1/2, then
+        // dt = log / A; otherwise log1p(x) = log(1 + x) with 1 + x as a double-double,
+        // then dt = r * (log1p / x).
+        const bool ratio = x < -0.5;
+        double L, yh, yl;
+        bool done;
+        if (ratio) {
+            yh = ue / up;
+            yl = 0.0;
+            done = ptcr::log_special(yh, &L);
+        } else {
+            const ptcr::dd y = ptcr::two_sum(1.0, x);
+            yh = y.h;
+            yl = y.l;
+            done = ptcr::log1p_special(x, &L);
+        }
+        if (!done) L = ptcr::log_dd_cr(yh, yl, &amb);
+        const double q = L / (ratio ? A : x);
+        dt = ratio ? q : r * q;
     }
     if (dt < 0.0) dt = 0.0;
     return dt;

@@ -20,8 +20,8 @@ extern "C" void ptcr_phases(int fn, const double* x, double* qh, double* ql, dou
         ptcr::dd q, a;
         if (fn == 1) {
             const ptcr::ExpRed R = ptcr::exp_reduce(x[i]);
-            q = ptcr::expm1_combine(R, ptcr::expm1_series_quick(R.r), 0);
-            a = ptcr::expm1_combine(R, ptcr::expm1_series_accurate(R.r), 0);
+            q = ptcr::expm1_combine<true>(R, ptcr::expm1_series_quick(R.r), 0);
+            a = ptcr::expm1_combine<false>(R, ptcr::expm1_series_accurate(R.r), 0);
         } else {
             const ptcr::dd y = fn == 0 ? ptcr::two_sum(1.0, x[i]) : ptcr::dd{x[i], 0.0};
             const ptcr::LogRed R = ptcr::log_reduce(y.h, y.l);
