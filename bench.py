@@ -10,10 +10,12 @@ resident in HBM before the timed region starts.
 Default workload (C2): 100x100x10 cells of 10x10x2 m, lognormal K with
 geometric mean 10 m/d, sigma^2 = 1, correlation length 5 cells, heads 10/0 m
 west/east, porosity 0.3; 1e6 particles released uniformly in the 10 western
-columns; endpoint mode, FP64, persistent work-queue kernel, packed cell
-records, hipGraph launch.  The same steps are also timed for the static
-one-thread-per-particle kernel and for the mixed-precision kernel, and the
-CPU oracle is timed on the host cores.
+columns; endpoint mode, FP64, packed cell records, hipGraph launch, with the
+autotuned launch of this device and workload (paper_2302_13590_amd/tuning.json:
+schedule, block size, processing order).  The same steps are also timed for the
+static and persistent kernels, the mixed-precision kernel and the pathline mode
+(count pass + record pass, one record per crossing), and the CPU oracle is timed
+on the host cores.
 
 Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
 """
@@ -128,6 +130,48 @@ class Case:
         kms = float(np.mean([s["kernel_ms"] for s in summ]))
         return dict(wall_s=wall, ms_per_step=1e3 * wall / steps, crossings_per_step=cross,
                     value=cross * steps / wall, kernel_ms=kms, summary=summ[0])
+
+    def time_pathline(self, precision, schedule_name, steps, warmup, **kw):
+        """One step = restore the state, the count pass (offsets), the record pass (one record
+        per crossing).  The record arrays are allocated once, before timing, at the size the
+        first count pass reports."""
+        pt, torch = self.pt, self.torch
+        n = self.pristine.n
+        offs = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+        oc = self.opts(precision, schedule_name, mode=pt.PT_PATHLINE, path_offsets=offs, path_count_only=1, **kw)
+        self.work.copy_(self.pristine)
+        m = self.step(oc)["path_records"]
+        arrs = dict(path_cell=torch.empty(m, dtype=torch.int32, device="cuda"),
+                    path_face=torch.empty(m, dtype=torch.int32, device="cuda"),
+                    path_t=torch.empty(m, dtype=torch.float64, device="cuda"),
+                    path_xyz=torch.empty((m, 3), dtype=torch.float64, device="cuda"))
+        orec = self.opts(precision, schedule_name, mode=pt.PT_PATHLINE, path_offsets=offs, path_count_only=0,
+                         path_cap=m, **arrs, **kw)
+
+        def one():
+            self.work.copy_(self.pristine)
+            a = pt.pt_track(self.grids, self.work, oc, stream=self.stream,
+                            group_offsets=self.w.group_offsets, group_grid=self.w.group_grid)
+            b = pt.pt_track(self.grids, self.work, orec, stream=self.stream,
+                            group_offsets=self.w.group_offsets, group_grid=self.w.group_grid)
+            sa, sb = pt.pt_results(a), pt.pt_results(b)
+            a.release()
+            b.release()
+            assert sa["path_records"] == m and sb["path_records"] == m and sb["path_dropped"] == 0
+            return sa, sb
+
+        for _ in range(warmup):
+            one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        summ = [one() for _ in range(steps)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        cross = summ[0][1]["crossings"]
+        return dict(value=cross * steps / wall, ms_per_step=1e3 * wall / steps, crossings_per_step=cross,
+                    records_per_step=m, record_bytes=m * 40 + (n + 1) * 8,
+                    count_ms=float(np.mean([a["kernel_ms"] for a, _ in summ])),
+                    record_ms=float(np.mean([b["kernel_ms"] for _, b in summ])))
 
     def release(self):
         for g in self.grids:
@@ -283,6 +327,15 @@ def main():
                 launch=p2, roofline_frac=roofline(r, n, prec, args.workload, s2, mode == "timeseries",
                                                   batched)["frac"])
             log("variant %s/%s: %.4g crossings/s" % (prec, s2, r["value"]))
+        if mode == "endpoint":
+            r = case.time_pathline(args.precision, sched, args.steps, args.warmup, **params)
+            variants["%s_pathline" % args.precision] = dict(
+                value=r["value"], ms_per_step=round(r["ms_per_step"], 4), count_ms=round(r["count_ms"], 4),
+                record_ms=round(r["record_ms"], 4), records_per_step=r["records_per_step"],
+                record_bytes_per_step=r["record_bytes"],
+                launch=params, note="count pass + record pass per step (one record of 40 B per crossing)")
+            log("variant pathline: %.4g crossings/s, count %.3f ms + record %.3f ms" % (
+                r["value"], r["count_ms"], r["record_ms"]))
     case.release()
 
     out = {

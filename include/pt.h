@@ -72,6 +72,8 @@ extern "C" {
 
 #define PT_ENDPOINT 0          /* final state only                                             */
 #define PT_TIMESERIES 1        /* plus positions at the snapshot times                         */
+#define PT_PATHLINE 2          /* plus one record per cell crossing (the particle's pathline:   *
+                                * the paper's third simulation type, Methods "MODPATH")        */
 
 #define PT_FP64 0              /* all arithmetic in FP64                                       */
 #define PT_MIXED 1             /* in-cell arithmetic in FP32; time, global position and the    *
@@ -144,7 +146,7 @@ typedef struct {
 
 /* ---- options ---------------------------------------------------------------------------- */
 typedef struct {
-    int32_t mode;                 /* PT_ENDPOINT | PT_TIMESERIES                                 */
+    int32_t mode;                 /* PT_ENDPOINT | PT_TIMESERIES | PT_PATHLINE                   */
     int32_t precision;            /* PT_FP64 | PT_MIXED                                          */
     int32_t schedule;             /* PT_SCHED_*                                                  */
     int32_t layout;               /* PT_LAYOUT_* (PT_MIXED requires CELL or AUTO)                */
@@ -174,6 +176,27 @@ typedef struct {
                                    * per atomic, >= 1, 0 = default (64)                          */
     int32_t sort;                 /* PT_SORT_*: processing order (never changes a result); the   *
                                    * ordered work is split into one contiguous part per die     */
+    /* PT_PATHLINE.  A pathline is the release point (the input state), one record per cell
+     * crossing made in this call, in crossing order, and the final state.  Records are stored
+     * particle by particle (CSR): those of particle p fill slots [path_offsets[p],
+     * path_offsets[p+1]).  Two calls with the same inputs produce them:
+     *   1. path_count_only = 1 (count pass): a dry run.  The particle arrays and out_xyz are
+     *      left untouched and no record is written; path_offsets[0] = 0 and path_offsets[p+1]
+     *      = the crossings particles 0..p make (exclusive scan of the per-particle counts), so
+     *      path_offsets[n] is the number of records.  pt_summary.path_records reports it.
+     *   2. path_count_only = 0 (record pass): tracks and writes the records.  Tracking is
+     *      deterministic, so particle p makes exactly path_offsets[p+1] - path_offsets[p]
+     *      crossings.  A record whose slot is not in [path_offsets[p], path_offsets[p+1]) or not
+     *      in [0, path_cap) is not written and is counted in pt_summary.path_dropped. */
+    int64_t* path_offsets;        /* device [n+1] int64: written by the count pass, read by the  *
+                                   * record pass                                                */
+    int32_t path_count_only;      /* 1: count pass, 0: record pass                               */
+    int64_t path_cap;             /* slots of each record array (record pass), >= 0              */
+    int32_t* path_cell;           /* device [path_cap] cell left at the crossing                 */
+    int32_t* path_face;           /* device [path_cap] face crossed: 2*axis + 1 for the high     *
+                                   * face (axis 0 = i, 1 = j, 2 = k)                            */
+    double* path_t;               /* device [path_cap] time of the crossing                      */
+    double* path_xyz;             /* device [path_cap][3] global position on the crossed face    */
 } pt_track_opts;
 
 /* Fill *o with the defaults: endpoint, FP64, auto schedule and layout, forward,
@@ -203,6 +226,8 @@ typedef struct {
                                    * could not be decided (input within 2^-96 of a rounding      *
                                    * boundary); the nearest double of a 2^-96-accurate value was *
                                    * used.  Expected 0.                                          */
+    int64_t path_records;         /* PT_PATHLINE: records counted (count pass) or written        */
+    int64_t path_dropped;         /* PT_PATHLINE record pass: records outside their slot range   */
 } pt_summary;
 
 /* Wait for the run, then fill *out.  Reports asynchronous device errors of

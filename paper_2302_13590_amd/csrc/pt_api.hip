@@ -118,6 +118,9 @@ struct pt_run {
     size_t d_tables_bytes = 0;
     void* d_sort = nullptr;             // processing order [n] + bucket histogram
     size_t d_sort_bytes = 0;
+    void* d_scan = nullptr;             // pathline count pass: tile sums of the offset scan
+    size_t d_scan_bytes = 0;
+    int path_pass = 0;                  // 0: no pathline, 1: count pass, 2: record pass
     void* h_tables = nullptr;
     size_t h_tables_bytes = 0;
     // cached graph: [reset counters, track] for one exact set of kernel arguments
@@ -141,6 +144,7 @@ void destroy_run(pt_run* r) {
     if (r->d_tables) (void)hipFree(r->d_tables);
     if (r->h_tables) (void)hipHostFree(r->h_tables);
     if (r->d_sort) (void)hipFree(r->d_sort);
+    if (r->d_scan) (void)hipFree(r->d_scan);
     delete r;
 }
 
@@ -204,11 +208,22 @@ int ensure_sort(pt_run* r, size_t bytes) {
     return PT_OK;
 }
 
+int ensure_scan(pt_run* r, size_t bytes) {
+    if (bytes <= r->d_scan_bytes) return PT_OK;
+    if (r->d_scan) (void)hipFree(r->d_scan);
+    r->d_scan = nullptr;
+    r->d_scan_bytes = 0;
+    HIP_TRY(hipMalloc(&r->d_scan, bytes));
+    r->d_scan_bytes = bytes;
+    return PT_OK;
+}
+
 // One kernel launch of a run: launched eagerly in order, or as a chain of graph nodes.
 struct Launch {
     const void* fn;
     dim3 grid, block;
     void* arg;
+    size_t bytes;   // size of *arg
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -272,7 +287,7 @@ hipError_t launch(const void* fn, dim3 grid, dim3 block, void* arg, hipStream_t 
 // =============================================================================================
 extern "C" {
 
-int pt_version(void) { return 100; }
+int pt_version(void) { return 101; }
 
 const char* pt_last_error(void) { return g_err.c_str(); }
 
@@ -412,7 +427,8 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     if (p->n > 0 && (!p->cell || !p->xi || !p->eta || !p->zeta || !p->t || !p->status || !p->ncross ||
                      !p->path_hash))
         return fail(PT_ERR_INVALID_ARG, "a particle state array is NULL");
-    if (o->mode != PT_ENDPOINT && o->mode != PT_TIMESERIES) return fail(PT_ERR_INVALID_ARG, "bad mode");
+    if (o->mode != PT_ENDPOINT && o->mode != PT_TIMESERIES && o->mode != PT_PATHLINE)
+        return fail(PT_ERR_INVALID_ARG, "bad mode");
     if (o->precision != PT_FP64 && o->precision != PT_MIXED) return fail(PT_ERR_INVALID_ARG, "bad precision");
     if (o->schedule < PT_SCHED_AUTO || o->schedule > PT_SCHED_PERSISTENT)
         return fail(PT_ERR_INVALID_ARG, "bad schedule");
@@ -439,6 +455,18 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
             if (!is_fin(o->snap_times[q])) return fail(PT_ERR_INVALID_ARG, "snap_times[%d] is not finite", q);
             if (q && o->snap_times[q] < o->snap_times[q - 1])
                 return fail(PT_ERR_INVALID_ARG, "snap_times must be non-decreasing");
+        }
+    }
+    const bool path = o->mode == PT_PATHLINE;
+    const bool path_count = path && o->path_count_only;
+    if (path) {
+        if (o->path_count_only != 0 && o->path_count_only != 1)
+            return fail(PT_ERR_INVALID_ARG, "path_count_only must be 0 or 1");
+        if (!o->path_offsets) return fail(PT_ERR_INVALID_ARG, "pathline needs path_offsets [n+1]");
+        if (!path_count) {
+            if (o->path_cap < 0) return fail(PT_ERR_INVALID_ARG, "path_cap must be >= 0");
+            if (o->path_cap > 0 && (!o->path_cell || !o->path_face || !o->path_t || !o->path_xyz))
+                return fail(PT_ERR_INVALID_ARG, "the record pass needs path_cell, path_face, path_t and path_xyz");
         }
     }
     const int32_t n_groups = p->n_groups;
@@ -474,7 +502,7 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     KernelKey key;
     key.precision = o->precision == PT_MIXED ? PMIX : P64;
     key.layout = o->layout == PT_LAYOUT_FACES ? L_FACES : L_CELL;
-    key.timeseries = ts ? 1 : 0;
+    key.out = ts ? O_SERIES : (path ? O_PATH : O_END);
     key.batched = batched ? 1 : 0;
     key.sched = o->schedule == PT_SCHED_STATIC ? S_STATIC : S_PERSISTENT;
     const void* fn = track_kernel(key);
@@ -502,6 +530,7 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     r->layout = key.layout == L_FACES ? PT_LAYOUT_FACES : PT_LAYOUT_CELL;
     r->block = block;
     r->grid = grid;
+    r->path_pass = path ? (path_count ? 1 : 2) : 0;
 
     // per-run tables: grid views, group table, snapshot times
     const size_t b_grids = batched ? align_up(sizeof(GridDev) * n_grids, 256) : 0;
@@ -580,6 +609,33 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     P.refill = o->refill ? o->refill : 1;
     P.steps_per_refill = o->steps_per_refill ? o->steps_per_refill : 1;
     P.chunk = o->chunk ? o->chunk : 64;
+    if (path) {
+        P.path_off = o->path_offsets;
+        P.path_count = path_count ? 1 : 0;
+        if (!path_count) {
+            P.path_cap = o->path_cap;
+            P.path_cell = o->path_cell;
+            P.path_face = o->path_face;
+            P.path_t = o->path_t;
+            P.path_xyz = o->path_xyz;
+        }
+    }
+
+    // count pass: the per-particle counts become offsets (scan of path_offsets[1..n])
+    ScanParams SC;
+    std::memset(&SC, 0, sizeof SC);
+    if (path_count) {
+        SC.v = o->path_offsets + 1;
+        SC.n = p->n;
+        SC.ntiles = (p->n + kScanTile - 1) / kScanTile;
+        SC.head = o->path_offsets;
+        rc = ensure_scan(r, sizeof(int64_t) * (size_t)std::max<int64_t>(1, SC.ntiles));
+        if (rc != PT_OK) {
+            destroy_run(r);
+            return rc;
+        }
+        SC.part = static_cast<int64_t*>(r->d_scan);
+    }
 
     // spatial ordering of the particles (counting sort by starting cell)
     SortParams SP;
@@ -613,17 +669,22 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     }
     Counters* cptr = r->d_counters;
     std::vector<Launch> seq;
-    seq.push_back({reset_kernel(), dim3(1), dim3(64), &cptr});
+    seq.push_back({reset_kernel(), dim3(1), dim3(64), &cptr, sizeof cptr});
     if (p->n > 0) {
         if (sort) {
             const unsigned nb = (unsigned)((p->n + 255) / 256);
             seq.push_back({sort_clear_kernel(), dim3(std::min(256u, (unsigned)(SP.nbuckets + 255) / 256)),
-                           dim3(256), &SP});
-            seq.push_back({sort_hist_kernel(), dim3(nb), dim3(256), &SP});
-            seq.push_back({sort_scan_kernel(), dim3(1), dim3(1024), &SP});
-            seq.push_back({sort_scatter_kernel(), dim3(nb), dim3(256), &SP});
+                           dim3(256), &SP, sizeof SP});
+            seq.push_back({sort_hist_kernel(), dim3(nb), dim3(256), &SP, sizeof SP});
+            seq.push_back({sort_scan_kernel(), dim3(1), dim3(1024), &SP, sizeof SP});
+            seq.push_back({sort_scatter_kernel(), dim3(nb), dim3(256), &SP, sizeof SP});
         }
-        seq.push_back({fn, dim3(grid), dim3(block), &P});
+        seq.push_back({fn, dim3(grid), dim3(block), &P, sizeof P});
+        if (path_count) seq.push_back({scan_tiles_kernel(), dim3((unsigned)SC.ntiles), dim3(kScanBlock), &SC, sizeof SC});
+    }
+    if (path_count) {
+        seq.push_back({scan_partials_kernel(), dim3(1), dim3(kScanBlock), &SC, sizeof SC});
+        if (SC.ntiles > 1) seq.push_back({scan_add_kernel(), dim3((unsigned)SC.ntiles), dim3(kScanBlock), &SC, sizeof SC});
     }
 
     hipError_t e = hipEventRecord(r->ev0, s);
@@ -632,7 +693,7 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
             // key: every launch's function, shape and argument bytes
             std::vector<unsigned char> gkey;
             for (const Launch& L : seq) {
-                const size_t bytes = (L.arg == &P) ? sizeof P : (L.arg == &SP) ? sizeof SP : sizeof cptr;
+                const size_t bytes = L.bytes;
                 const unsigned char* a = static_cast<const unsigned char*>(L.arg);
                 const unsigned char* f = reinterpret_cast<const unsigned char*>(&L.fn);
                 gkey.insert(gkey.end(), f, f + sizeof L.fn);
@@ -715,6 +776,11 @@ int pt_results(pt_run* r, pt_summary* out) {
     out->block = r->block;
     out->grid = r->grid;
     out->cr_ambiguous = (int64_t)c.cr_ambiguous;
+    if (r->path_pass == 1) out->path_records = out->crossings;
+    if (r->path_pass == 2) {
+        out->path_dropped = (int64_t)c.path_dropped;
+        out->path_records = out->crossings - out->path_dropped;
+    }
     return PT_OK;
 }
 

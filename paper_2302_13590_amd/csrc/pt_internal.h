@@ -62,7 +62,8 @@ struct Counters {
     unsigned long long status[8];
     unsigned long long cr_ambiguous;  // correctly rounded evaluations left undecided
     unsigned long long queue[kXcd];   // next slot handed out in each die's segment
-    unsigned long long pad[14];
+    unsigned long long path_dropped;  // pathline records outside their slot range
+    unsigned long long pad[13];
 };
 static_assert(sizeof(Counters) == 32 * 8, "Counters is 32 words");
 
@@ -100,6 +101,33 @@ struct TrackParams {
     // are split into kXcd contiguous segments, one per die, so that a die's L2 sees one
     // spatially coherent part of the particles.
     const int32_t* order;
+    // Pathline output (O_PATH kernels).  Count pass (path_count): path_off[p+1] receives the
+    // crossings of particle p and no state is written back.  Record pass: the records of p go to
+    // slots [path_off[p], path_off[p+1]) that are also below path_cap.
+    int64_t* path_off;
+    int32_t path_count;
+    int32_t pad_path;
+    int64_t path_cap;
+    int32_t* path_cell;
+    int32_t* path_face;
+    double* path_t;
+    double* path_xyz;
+};
+
+// Output form of a tracking kernel (template argument).
+enum : int { O_END = 0, O_SERIES = 1, O_PATH = 2 };
+
+// Inclusive prefix sum of v[0..n) in place (the pathline offsets), three kernels: tile sums,
+// a scan of the tile sums, then the tile offsets added.
+constexpr int kScanBlock = 1024;
+constexpr int kScanPer = 8;
+constexpr int64_t kScanTile = (int64_t)kScanBlock * kScanPer;
+struct ScanParams {
+    int64_t* v;
+    int64_t n;
+    int64_t* part;     // [ceil(n / kScanTile)] tile sums, then their exclusive scan
+    int64_t ntiles;
+    int64_t* head;     // element written 0 before v (path_off[0]); may be null
 };
 
 // Spatial ordering of particles by starting cell (counting sort into buckets of cells).
@@ -124,7 +152,7 @@ enum Layout { L_FACES = 1, L_CELL = 2 };
 enum Sched { S_STATIC = 1, S_PERSISTENT = 2 };
 
 struct KernelKey {
-    int precision, layout, timeseries, batched, sched;
+    int precision, layout, out, batched, sched;   // out: O_END / O_SERIES / O_PATH
 };
 
 // Kernel lookup (defined in pt_kernels.hip).
@@ -134,8 +162,10 @@ const void* sort_clear_kernel();
 const void* sort_hist_kernel();
 const void* sort_scan_kernel();
 const void* sort_scatter_kernel();
+const void* scan_tiles_kernel();
+const void* scan_partials_kernel();
+const void* scan_add_kernel();
 const void* build_kernel();
-const void* check_kernel();
 
 // Grid build kernel arguments.
 struct BuildParams {

@@ -337,12 +337,15 @@ struct Lane {
     int32_t ncross;
     int32_t ks;         // next snapshot index
     unsigned amb;       // undecided roundings of the correctly rounded functions
+    unsigned drop;      // pathline records that had no slot
     unsigned long long hash;
     double t;
     double s_next;      // time of snapshot ks (+inf past the last)
     R x[3];             // local coordinates
     R v1[3], v2[3];     // packed layout: the current cell's face velocities (low, high face)
     int32_t fl;         // packed layout: the current cell's flag word
+    int32_t nc0;        // pathline: crossings before this call
+    int64_t pq, pend;   // pathline record pass: next slot, end of the particle's slots
 };
 
 template <bool BATCHED>
@@ -473,7 +476,7 @@ __device__ __forceinline__ int32_t find_group(const TrackParams& P, int64_t pid)
 
 // Release checks (S0).  Returns 0 when the particle is to be tracked, ST_SKIP when it is
 // not tracked by this call, or a final status.
-template <int PREC, int LAYOUT, bool TS, bool BATCHED>
+template <int PREC, int LAYOUT, int OUT, bool BATCHED>
 __device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap) {
     using R = typename Real<PREC>::T;
     const int64_t p = L.pid;
@@ -484,6 +487,12 @@ __device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap
     const int64_t ncell = (int64_t)G.nx * G.ny * G.nz;
     const int32_t c = P.cell[p];
     if (st != ST_ACTIVE && st != ST_MAX_TIME) {
+        if constexpr (OUT == O_PATH) {
+            if (P.path_count) {
+                P.path_off[p + 1] = 0;   // dry run: nothing else is written
+                return ST_SKIP;
+            }
+        }
         if (P.out_xyz) {
             double* o = P.out_xyz + 3 * p;
             if (st == ST_INVALID || c < 0 || c >= ncell) {
@@ -512,7 +521,7 @@ __device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap
     if (!(a >= 0.0 && a <= 1.0) || !(b >= 0.0 && b <= 1.0) || !(d >= 0.0 && d <= 1.0)) bad = true;
     if (!(t == t) || __builtin_isinf(t)) bad = true;
     if (bad) {
-        if constexpr (TS) {
+        if constexpr (OUT == O_SERIES) {
             L.ks = 0;
             nan_rest(L, P);
         }
@@ -531,7 +540,15 @@ __device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap
     L.t = t;
     L.ncross = P.ncross[p];
     L.hash = P.hash[p];
-    if constexpr (TS) {
+    if constexpr (OUT == O_PATH) {
+        L.nc0 = L.ncross;
+        if (!P.path_count) {
+            L.pq = P.path_off[p];
+            const int64_t e = P.path_off[p + 1];
+            L.pend = (e < P.path_cap) ? e : P.path_cap;
+        }
+    }
+    if constexpr (OUT == O_SERIES) {
         double* row = P.snap_xyz + p * (int64_t)P.n_snap * 3;
         int32_t q = 0;
         while (q < P.n_snap && snap[q] < t) {
@@ -547,11 +564,17 @@ __device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap
 }
 
 // Write the final state of a tracked particle.
-template <int PREC, bool TS, bool BATCHED>
+template <int PREC, int OUT, bool BATCHED>
 __device__ void finish(Lane<PREC>& L, int32_t st, const TrackParams& P, unsigned int* s_hist) {
     const int64_t p = L.pid;
-    P.status[p] = st;
     atomicAdd(&s_hist[st], 1u);
+    if constexpr (OUT == O_PATH) {
+        if (P.path_count) {   // dry run: the crossing count is the only output
+            P.path_off[p + 1] = (st == ST_INVALID) ? 0 : (int64_t)(L.ncross - L.nc0);
+            return;
+        }
+    }
+    P.status[p] = st;
     if (st == ST_INVALID) {
         if (P.out_xyz) put_nan3(P.out_xyz + 3 * p);
         return;
@@ -567,11 +590,11 @@ __device__ void finish(Lane<PREC>& L, int32_t st, const TrackParams& P, unsigned
         const GridDev& G = grid_of<BATCHED>(P, L.g);
         global_xyz(G, L.i, L.j, L.k, (double)L.x[0], (double)L.x[1], (double)L.x[2], P.out_xyz + 3 * p);
     }
-    if constexpr (TS) nan_rest(L, P);
+    if constexpr (OUT == O_SERIES) nan_rest(L, P);
 }
 
 // One cell crossing (S1-S7).  Returns 0 to continue, or the final status.
-template <int PREC, int LAYOUT, bool TS, bool BATCHED>
+template <int PREC, int LAYOUT, int OUT, bool BATCHED>
 __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& P, const double* snap,
                                               unsigned long long& crossings) {
     using R = typename Real<PREC>::T;
@@ -610,13 +633,13 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
 
     // time limit; a face reached exactly at t_max is crossed
     if (axis < 0 && __builtin_isinf(P.t_max)) {
-        if constexpr (TS) write_snaps<PREC>(L, G, u1, u2, P, snap, dinf(), true);
+        if constexpr (OUT == O_SERIES) write_snaps<PREC>(L, G, u1, u2, P, snap, dinf(), true);
         return ST_STRANDED;
     }
     const double t_exit = L.t + dt;
     if (t_exit > P.t_max) {
         const double tau = P.t_max - L.t;
-        if constexpr (TS) write_snaps<PREC>(L, G, u1, u2, P, snap, P.t_max, true);
+        if constexpr (OUT == O_SERIES) write_snaps<PREC>(L, G, u1, u2, P, snap, P.t_max, true);
 #pragma unroll
         for (int a = 0; a < 3; ++a) L.x[a] = adv<PREC>(u1[a], u2[a], L.x[a], tau, L.amb);
         L.t = P.t_max;
@@ -628,7 +651,7 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
     const int32_t step = hi ? 1 : -1;
 
     // advance to the exit face: the two other axes move analytically
-    if constexpr (TS) write_snaps<PREC>(L, G, u1, u2, P, snap, t_exit, false);
+    if constexpr (OUT == O_SERIES) write_snaps<PREC>(L, G, u1, u2, P, snap, t_exit, false);
     {
         const int a1 = (axis == 0) ? 1 : 0;
         const int a2 = (axis == 2) ? 1 : 2;
@@ -648,6 +671,21 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
     L.ncross += 1;
     crossings += 1;
     L.hash = (L.hash ^ (unsigned long long)(uint32_t)L.c) * kFnvPrime;
+    if constexpr (OUT == O_PATH) {
+        // pathline record: the cell left, the face, the time and the position on the face
+        if (!P.path_count) {
+            const int64_t q = L.pq++;
+            if (q >= 0 && q < L.pend) {
+                P.path_cell[q] = L.c;
+                P.path_face[q] = f;
+                P.path_t[q] = L.t;
+                global_xyz(G, L.i, L.j, L.k, (double)L.x[0], (double)L.x[1], (double)L.x[2],
+                           P.path_xyz + 3 * q);
+            } else {
+                L.drop += 1u;
+            }
+        }
+    }
 
     // transfer to the neighbour across the exit face
     int32_t nfl_sink;
@@ -689,6 +727,7 @@ struct BlockCounters {
     unsigned int hist[8];
     unsigned long long cross;
     unsigned int amb;
+    unsigned int drop;
 };
 
 template <bool TS> struct BlockShared;
@@ -703,6 +742,7 @@ __device__ __forceinline__ const double* block_setup(BlockShared<TS>& S, const T
     if (threadIdx.x == 0) {
         S.cross = 0ull;
         S.amb = 0u;
+        S.drop = 0u;
     }
     ptcr::lds_tables_init();
     const double* snap = P.snap_times;
@@ -717,26 +757,30 @@ __device__ __forceinline__ const double* block_setup(BlockShared<TS>& S, const T
 }
 
 __device__ __forceinline__ void block_flush(BlockCounters& S, const TrackParams& P,
-                                            unsigned long long crossings, unsigned amb) {
+                                            unsigned long long crossings, unsigned amb,
+                                            unsigned drop) {
     // wave-level reduction of the crossing count, one LDS atomic per wave
     for (int off = 32; off > 0; off >>= 1) crossings += __shfl_down(crossings, off, 64);
     if ((threadIdx.x & 63) == 0) atomicAdd(&S.cross, crossings);
     if (amb) atomicAdd(&S.amb, amb);
+    if (drop) atomicAdd(&S.drop, drop);
     __syncthreads();
     if (threadIdx.x == 0 && S.amb) atomicAdd(&P.counters->cr_ambiguous, (unsigned long long)S.amb);
+    if (threadIdx.x == 0 && S.drop) atomicAdd(&P.counters->path_dropped, (unsigned long long)S.drop);
     if (threadIdx.x < 8 && S.hist[threadIdx.x])
         atomicAdd(&P.counters->status[threadIdx.x], (unsigned long long)S.hist[threadIdx.x]);
     if (threadIdx.x == 0 && S.cross) atomicAdd(&P.counters->crossings, S.cross);
 }
 
 // ---------------------------------------------------------------------------------------------
-template <int PREC, int LAYOUT, bool TS, bool BATCHED>
+template <int PREC, int LAYOUT, int OUT, bool BATCHED>
 __global__ void __launch_bounds__(kBlock) k_track_static(TrackParams P) {
-    __shared__ BlockShared<TS> S;
-    const double* snap = block_setup<TS>(S, P);
+    __shared__ BlockShared<OUT == O_SERIES> S;
+    const double* snap = block_setup<OUT == O_SERIES>(S, P);
     unsigned long long crossings = 0;
     Lane<PREC> L;
     L.amb = 0u;
+    L.drop = 0u;
     // die d = blockIdx.x mod 8 takes the d-th contiguous eighth of the slots (gridDim.x is a
     // multiple of 8)
     const int64_t per_die = (int64_t)gridDim.x / kXcd;
@@ -744,17 +788,17 @@ __global__ void __launch_bounds__(kBlock) k_track_static(TrackParams P) {
     const int64_t slot = blk * blockDim.x + threadIdx.x;
     if (slot < P.n) {
         L.pid = P.order ? (int64_t)P.order[slot] : slot;
-        int32_t st = begin<PREC, LAYOUT, TS, BATCHED>(L, P, snap);
-        while (st == 0) st = track_step<PREC, LAYOUT, TS, BATCHED>(L, P, snap, crossings);
-        if (st > 0) finish<PREC, TS, BATCHED>(L, st, P, S.hist);
+        int32_t st = begin<PREC, LAYOUT, OUT, BATCHED>(L, P, snap);
+        while (st == 0) st = track_step<PREC, LAYOUT, OUT, BATCHED>(L, P, snap, crossings);
+        if (st > 0) finish<PREC, OUT, BATCHED>(L, st, P, S.hist);
     }
-    block_flush(S, P, crossings, L.amb);
+    block_flush(S, P, crossings, L.amb, L.drop);
 }
 
-template <int PREC, int LAYOUT, bool TS, bool BATCHED>
+template <int PREC, int LAYOUT, int OUT, bool BATCHED>
 __global__ void __launch_bounds__(kBlock) k_track_persistent(TrackParams P) {
-    __shared__ BlockShared<TS> S;
-    const double* snap = block_setup<TS>(S, P);
+    __shared__ BlockShared<OUT == O_SERIES> S;
+    const double* snap = block_setup<OUT == O_SERIES>(S, P);
     unsigned long long crossings = 0;
     const unsigned long long n = (unsigned long long)P.n;
     const int refill = P.refill;
@@ -771,6 +815,7 @@ __global__ void __launch_bounds__(kBlock) k_track_persistent(TrackParams P) {
     int tried = 0;           // segments found empty so far (wave-uniform)
     Lane<PREC> L;
     L.amb = 0u;
+    L.drop = 0u;
     L.pid = -1;
     for (;;) {
         const unsigned long long idle = __ballot(L.pid < 0);
@@ -803,9 +848,9 @@ __global__ void __launch_bounds__(kBlock) k_track_persistent(TrackParams P) {
                 else if (rank - avail < nlen) slot = (long long)(nbase + (rank - avail));
                 if (slot >= 0) {
                     L.pid = P.order ? (int64_t)P.order[slot] : slot;
-                    const int32_t st = begin<PREC, LAYOUT, TS, BATCHED>(L, P, snap);
+                    const int32_t st = begin<PREC, LAYOUT, OUT, BATCHED>(L, P, snap);
                     if (st != 0) {
-                        if (st > 0) finish<PREC, TS, BATCHED>(L, st, P, S.hist);
+                        if (st > 0) finish<PREC, OUT, BATCHED>(L, st, P, S.hist);
                         L.pid = -1;
                     }
                 }
@@ -824,15 +869,15 @@ __global__ void __launch_bounds__(kBlock) k_track_persistent(TrackParams P) {
         }
         for (int s = 0; s < steps; ++s) {
             if (L.pid >= 0) {
-                const int32_t st = track_step<PREC, LAYOUT, TS, BATCHED>(L, P, snap, crossings);
+                const int32_t st = track_step<PREC, LAYOUT, OUT, BATCHED>(L, P, snap, crossings);
                 if (st != 0) {
-                    finish<PREC, TS, BATCHED>(L, st, P, S.hist);
+                    finish<PREC, OUT, BATCHED>(L, st, P, S.hist);
                     L.pid = -1;
                 }
             }
         }
     }
-    block_flush(S, P, crossings, L.amb);
+    block_flush(S, P, crossings, L.amb, L.drop);
 }
 
 __global__ void k_reset(Counters* c) {
@@ -906,6 +951,69 @@ __global__ void __launch_bounds__(256) k_sort_scatter(SortParams S) {
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Pathline offsets: inclusive prefix sum, in place, of the per-particle crossing counts written
+// by the count pass (v = path_offsets + 1), and path_offsets[0] = 0.
+
+// Block-wide inclusive scan of one value per thread (Hillis-Steele in LDS).
+__device__ __forceinline__ int64_t block_scan(int64_t* part, int64_t x) {
+    part[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+        const int64_t a = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += a;
+        __syncthreads();
+    }
+    return part[threadIdx.x];
+}
+
+// Tile b (kScanTile elements): scan within the tile, tile total to part[b].
+__global__ void __launch_bounds__(kScanBlock) k_scan_tiles(ScanParams S) {
+    __shared__ int64_t part[kScanBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int64_t v[kScanPer];
+    int64_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        v[q] = (base + q < S.n) ? S.v[base + q] : 0;
+        sum += v[q];
+    }
+    const int64_t incl = block_scan(part, sum);
+    int64_t run = incl - sum;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        run += v[q];
+        if (base + q < S.n) S.v[base + q] = run;
+    }
+    if (threadIdx.x == kScanBlock - 1) S.part[blockIdx.x] = incl;
+}
+
+// One workgroup: exclusive scan of the tile totals; writes the leading zero.
+__global__ void __launch_bounds__(kScanBlock) k_scan_partials(ScanParams S) {
+    __shared__ int64_t part[kScanBlock];
+    const int64_t per = (S.ntiles + kScanBlock - 1) / kScanBlock;
+    const int64_t lo = (int64_t)threadIdx.x * per;
+    const int64_t hi = (lo + per < S.ntiles) ? lo + per : S.ntiles;
+    int64_t sum = 0;
+    for (int64_t q = lo; q < hi; ++q) sum += S.part[q];
+    int64_t run = block_scan(part, sum) - sum;
+    for (int64_t q = lo; q < hi; ++q) {
+        const int64_t h = S.part[q];
+        S.part[q] = run;
+        run += h;
+    }
+    if (threadIdx.x == 0 && S.head) *S.head = 0;
+}
+
+// Tile b adds the total of the tiles before it.
+__global__ void __launch_bounds__(kScanBlock) k_scan_add(ScanParams S) {
+    const int64_t add = S.part[blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    for (int64_t q = threadIdx.x; q < kScanTile; q += kScanBlock)
+        if (base + q < S.n) S.v[base + q] += add;
+}
+
 // Grid load: validate the field and build both packed records of every cell.
 __global__ void __launch_bounds__(256) k_build(BuildParams B) {
     const GridDev& G = B.g;
@@ -965,28 +1073,30 @@ __global__ void __launch_bounds__(256) k_build(BuildParams B) {
     B.rec32[c] = r32;
 }
 
-template <int PREC, int LAYOUT, bool TS, bool BATCHED>
+template <int PREC, int LAYOUT, int OUT, bool BATCHED>
 const void* pick_sched(int sched) {
-    if (sched == S_STATIC) return reinterpret_cast<const void*>(&k_track_static<PREC, LAYOUT, TS, BATCHED>);
-    return reinterpret_cast<const void*>(&k_track_persistent<PREC, LAYOUT, TS, BATCHED>);
+    if (sched == S_STATIC) return reinterpret_cast<const void*>(&k_track_static<PREC, LAYOUT, OUT, BATCHED>);
+    return reinterpret_cast<const void*>(&k_track_persistent<PREC, LAYOUT, OUT, BATCHED>);
 }
 
-template <int PREC, int LAYOUT, bool TS>
+template <int PREC, int LAYOUT, int OUT>
 const void* pick_batched(const KernelKey& k) {
-    return k.batched ? pick_sched<PREC, LAYOUT, TS, true>(k.sched) : pick_sched<PREC, LAYOUT, TS, false>(k.sched);
+    return k.batched ? pick_sched<PREC, LAYOUT, OUT, true>(k.sched) : pick_sched<PREC, LAYOUT, OUT, false>(k.sched);
 }
 
 template <int PREC, int LAYOUT>
-const void* pick_ts(const KernelKey& k) {
-    return k.timeseries ? pick_batched<PREC, LAYOUT, true>(k) : pick_batched<PREC, LAYOUT, false>(k);
+const void* pick_out(const KernelKey& k) {
+    if (k.out == O_SERIES) return pick_batched<PREC, LAYOUT, O_SERIES>(k);
+    if (k.out == O_PATH) return pick_batched<PREC, LAYOUT, O_PATH>(k);
+    return pick_batched<PREC, LAYOUT, O_END>(k);
 }
 
 }  // namespace
 
 const void* track_kernel(const KernelKey& k) {
-    if (k.precision == PMIX) return pick_ts<PMIX, L_CELL>(k);
-    if (k.layout == L_FACES) return pick_ts<P64, L_FACES>(k);
-    return pick_ts<P64, L_CELL>(k);
+    if (k.precision == PMIX) return pick_out<PMIX, L_CELL>(k);
+    if (k.layout == L_FACES) return pick_out<P64, L_FACES>(k);
+    return pick_out<P64, L_CELL>(k);
 }
 
 const void* reset_kernel() { return reinterpret_cast<const void*>(&k_reset); }
@@ -994,6 +1104,9 @@ const void* sort_clear_kernel() { return reinterpret_cast<const void*>(&k_sort_c
 const void* sort_hist_kernel() { return reinterpret_cast<const void*>(&k_sort_hist); }
 const void* sort_scan_kernel() { return reinterpret_cast<const void*>(&k_sort_scan); }
 const void* sort_scatter_kernel() { return reinterpret_cast<const void*>(&k_sort_scatter); }
+const void* scan_tiles_kernel() { return reinterpret_cast<const void*>(&k_scan_tiles); }
+const void* scan_partials_kernel() { return reinterpret_cast<const void*>(&k_scan_partials); }
+const void* scan_add_kernel() { return reinterpret_cast<const void*>(&k_scan_add); }
 const void* build_kernel() { return reinterpret_cast<const void*>(&k_build); }
 
 }  // namespace pt

@@ -24,7 +24,7 @@ ERR_NAMES = {-1: "PT_ERR_INVALID_ARG", -2: "PT_ERR_BAD_HANDLE", -3: "PT_ERR_OOM"
 STATUS_NAMES = ["ACTIVE", "BOUNDARY", "SINK", "MAX_TIME", "STEP_CAP", "STRANDED", "INVALID_START",
                 "INACTIVE_NEIGHBOR"]
 PT_MEM_HOST, PT_MEM_DEVICE = 0, 1
-PT_ENDPOINT, PT_TIMESERIES = 0, 1
+PT_ENDPOINT, PT_TIMESERIES, PT_PATHLINE = 0, 1, 2
 PT_FP64, PT_MIXED = 0, 1
 PT_SCHED_AUTO, PT_SCHED_STATIC, PT_SCHED_PERSISTENT = 0, 1, 2
 PT_LAYOUT_AUTO, PT_LAYOUT_FACES, PT_LAYOUT_CELL = 0, 1, 2
@@ -57,14 +57,17 @@ class pt_track_opts(ctypes.Structure):
                 ("snap_xyz", _p), ("out_xyz", _p), ("use_graph", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("refill", ctypes.c_int32), ("steps_per_refill", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("sort", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("sort", ctypes.c_int32),
+                ("path_offsets", _p), ("path_count_only", ctypes.c_int32), ("path_cap", ctypes.c_int64),
+                ("path_cell", _p), ("path_face", _p), ("path_t", _p), ("path_xyz", _p)]
 
 
 class pt_summary(ctypes.Structure):
     _fields_ = [("crossings", ctypes.c_int64), ("n_tracked", ctypes.c_int64),
                 ("status_count", ctypes.c_int64 * 8), ("kernel_ms", ctypes.c_double),
                 ("schedule", ctypes.c_int32), ("layout", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("cr_ambiguous", ctypes.c_int64)]
+                ("grid", ctypes.c_int32), ("cr_ambiguous", ctypes.c_int64),
+                ("path_records", ctypes.c_int64), ("path_dropped", ctypes.c_int64)]
 
 
 EXPORTS = ["pt_load_grid", "pt_track", "pt_results", "pt_release", "pt_last_error", "pt_default_opts",
@@ -244,7 +247,8 @@ def pt_default_opts() -> pt_track_opts:
 def make_opts(mode=PT_ENDPOINT, precision=PT_FP64, schedule=PT_SCHED_AUTO, layout=PT_LAYOUT_AUTO,
               direction=1, stop_at_sink=1, t_max=math.inf, max_steps=1 << 20, snap_times=None,
               snap_xyz=None, out_xyz=None, use_graph=0, block=0, blocks_per_cu=0, refill=0,
-              steps_per_refill=0, chunk=0, sort=0):
+              steps_per_refill=0, chunk=0, sort=0, path_offsets=None, path_count_only=0, path_cap=0,
+              path_cell=None, path_face=None, path_t=None, path_xyz=None):
     o = pt_default_opts()
     o.mode, o.precision, o.schedule, o.layout = mode, precision, schedule, layout
     o.direction, o.stop_at_sink, o.t_max, o.max_steps = direction, stop_at_sink, t_max, max_steps
@@ -258,6 +262,9 @@ def make_opts(mode=PT_ENDPOINT, precision=PT_FP64, schedule=PT_SCHED_AUTO, layou
     o.out_xyz = _ptr(out_xyz)
     o.use_graph, o.block, o.blocks_per_cu, o.refill, o.steps_per_refill, o.chunk, o.sort = (
         use_graph, block, blocks_per_cu, refill, steps_per_refill, chunk, sort)
+    o.path_offsets, o.path_count_only, o.path_cap = _ptr(path_offsets), path_count_only, path_cap
+    o.path_cell, o.path_face, o.path_t, o.path_xyz = (_ptr(path_cell), _ptr(path_face), _ptr(path_t),
+                                                      _ptr(path_xyz))
     o._keep = keep
     return o
 
@@ -290,7 +297,7 @@ def pt_results(run: Run) -> dict:
     _check(load_library().pt_results(run.handle, ctypes.byref(s)))
     return dict(crossings=s.crossings, n_tracked=s.n_tracked, status_count=list(s.status_count),
                 kernel_ms=s.kernel_ms, schedule=s.schedule, layout=s.layout, block=s.block, grid=s.grid,
-                cr_ambiguous=s.cr_ambiguous)
+                cr_ambiguous=s.cr_ambiguous, path_records=s.path_records, path_dropped=s.path_dropped)
 
 
 # --------------------------------------------------------------------------------------------- helper
@@ -304,3 +311,35 @@ def track(grids, particles: DeviceParticles, stream=None, group_offsets=None, gr
         return pt_results(run)
     finally:
         run.release()
+
+
+@dataclasses.dataclass
+class Pathlines:
+    """Pathline records in CSR form: those of particle p are rows offsets[p]:offsets[p+1]."""
+    offsets: torch.Tensor   # int64 [n+1]
+    cell: torch.Tensor      # int32 [m] cell left
+    face: torch.Tensor      # int32 [m] 2*axis + 1 for the high face
+    t: torch.Tensor         # float64 [m] time of the crossing
+    xyz: torch.Tensor       # float64 [m, 3] global position on the face
+
+
+def track_pathlines(grids, particles: DeviceParticles, stream=None, group_offsets=None, group_grid=None,
+                    **opt):
+    """Pathline run: the count pass (offsets), device buffers of the reported size, the record pass.
+
+    Returns (summary of the record pass, Pathlines).  Both passes run in the library; this
+    helper only allocates the output tensors between them."""
+    dev = particles.cell.device
+    offsets = torch.empty(particles.n + 1, dtype=torch.int64, device=dev)
+    kw = dict(opt, mode=PT_PATHLINE, path_offsets=offsets)
+    s0 = track(grids, particles, stream=stream, group_offsets=group_offsets, group_grid=group_grid,
+               path_count_only=1, **kw)
+    m = s0["path_records"]
+    out = Pathlines(offsets, torch.empty(m, dtype=torch.int32, device=dev),
+                    torch.empty(m, dtype=torch.int32, device=dev),
+                    torch.empty(m, dtype=torch.float64, device=dev),
+                    torch.empty((m, 3), dtype=torch.float64, device=dev))
+    s = track(grids, particles, stream=stream, group_offsets=group_offsets, group_grid=group_grid,
+              path_count_only=0, path_cap=m, path_cell=out.cell, path_face=out.face, path_t=out.t,
+              path_xyz=out.xyz, **kw)
+    return s, out
