@@ -141,12 +141,9 @@ class Case:
         oc = self.opts(precision, schedule_name, mode=pt.PT_PATHLINE, path_offsets=offs, path_count_only=1, **kw)
         self.work.copy_(self.pristine)
         m = self.step(oc)["path_records"]
-        arrs = dict(path_cell=torch.empty(m, dtype=torch.int32, device="cuda"),
-                    path_face=torch.empty(m, dtype=torch.int32, device="cuda"),
-                    path_t=torch.empty(m, dtype=torch.float64, device="cuda"),
-                    path_xyz=torch.empty((m, 3), dtype=torch.float64, device="cuda"))
+        records = pt.path_record_buffer(m)
         orec = self.opts(precision, schedule_name, mode=pt.PT_PATHLINE, path_offsets=offs, path_count_only=0,
-                         path_cap=m, **arrs, **kw)
+                         path_cap=m, path_records=records, **kw)
 
         def one():
             self.work.copy_(self.pristine)

@@ -144,6 +144,15 @@ typedef struct {
     const int32_t* group_grid;    /* host [n_groups], each in [0, n_grids)                       */
 } pt_particles;
 
+/* ---- pathline record (PT_PATHLINE) ----------------------------------------------------- */
+typedef struct {
+    double t;                     /* time of the crossing                                        */
+    double x, y, z;               /* global position on the crossed face                         */
+    int32_t cell;                 /* cell left                                                   */
+    int32_t face;                 /* face crossed: 2*axis + 1 for the high face (axis 0 = i,     *
+                                   * 1 = j, 2 = k)                                              */
+} pt_path_record;                 /* 40 bytes, 8-byte aligned                                    */
+
 /* ---- options ---------------------------------------------------------------------------- */
 typedef struct {
     int32_t mode;                 /* PT_ENDPOINT | PT_TIMESERIES | PT_PATHLINE                   */
@@ -178,7 +187,7 @@ typedef struct {
                                    * ordered work is split into one contiguous part per die     */
     /* PT_PATHLINE.  A pathline is the release point (the input state), one record per cell
      * crossing made in this call, in crossing order, and the final state.  Records are stored
-     * particle by particle (CSR): those of particle p fill slots [path_offsets[p],
+     * particle by particle (CSR): those of particle p fill path_records[path_offsets[p] ..
      * path_offsets[p+1]).  Two calls with the same inputs produce them:
      *   1. path_count_only = 1 (count pass): a dry run.  The particle arrays and out_xyz are
      *      left untouched and no record is written; path_offsets[0] = 0 and path_offsets[p+1]
@@ -191,12 +200,8 @@ typedef struct {
     int64_t* path_offsets;        /* device [n+1] int64: written by the count pass, read by the  *
                                    * record pass                                                */
     int32_t path_count_only;      /* 1: count pass, 0: record pass                               */
-    int64_t path_cap;             /* slots of each record array (record pass), >= 0              */
-    int32_t* path_cell;           /* device [path_cap] cell left at the crossing                 */
-    int32_t* path_face;           /* device [path_cap] face crossed: 2*axis + 1 for the high     *
-                                   * face (axis 0 = i, 1 = j, 2 = k)                            */
-    double* path_t;               /* device [path_cap] time of the crossing                      */
-    double* path_xyz;             /* device [path_cap][3] global position on the crossed face    */
+    int64_t path_cap;             /* records path_records can hold (record pass), >= 0           */
+    pt_path_record* path_records; /* device [path_cap] (record pass; may be NULL if path_cap = 0) */
 } pt_track_opts;
 
 /* Fill *o with the defaults: endpoint, FP64, auto schedule and layout, forward,

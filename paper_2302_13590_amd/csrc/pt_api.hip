@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -16,6 +17,10 @@
 #include "pt_internal.h"
 
 using namespace pt;
+
+static_assert(sizeof(pt_path_record) == sizeof(PathRec) && offsetof(pt_path_record, cell) == offsetof(PathRec, cell) &&
+                  offsetof(pt_path_record, face) == offsetof(PathRec, face) && offsetof(pt_path_record, z) == offsetof(PathRec, z),
+              "pt_path_record and the kernels' record differ");
 
 // ---------------------------------------------------------------------------------------------
 // errors
@@ -465,8 +470,8 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
         if (!o->path_offsets) return fail(PT_ERR_INVALID_ARG, "pathline needs path_offsets [n+1]");
         if (!path_count) {
             if (o->path_cap < 0) return fail(PT_ERR_INVALID_ARG, "path_cap must be >= 0");
-            if (o->path_cap > 0 && (!o->path_cell || !o->path_face || !o->path_t || !o->path_xyz))
-                return fail(PT_ERR_INVALID_ARG, "the record pass needs path_cell, path_face, path_t and path_xyz");
+            if (o->path_cap > 0 && !o->path_records)
+                return fail(PT_ERR_INVALID_ARG, "the record pass needs path_records");
         }
     }
     const int32_t n_groups = p->n_groups;
@@ -614,10 +619,7 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
         P.path_count = path_count ? 1 : 0;
         if (!path_count) {
             P.path_cap = o->path_cap;
-            P.path_cell = o->path_cell;
-            P.path_face = o->path_face;
-            P.path_t = o->path_t;
-            P.path_xyz = o->path_xyz;
+            P.path_rec = reinterpret_cast<PathRec*>(o->path_records);
         }
     }
 

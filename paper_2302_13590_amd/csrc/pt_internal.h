@@ -67,6 +67,13 @@ struct Counters {
 };
 static_assert(sizeof(Counters) == 32 * 8, "Counters is 32 words");
 
+// One pathline record (the layout of pt_path_record).
+struct PathRec {
+    double t, x, y, z;
+    int32_t cell, face;
+};
+static_assert(sizeof(PathRec) == 40, "PathRec is 40 bytes");
+
 struct TrackParams {
     int64_t n;
     int32_t* cell;
@@ -108,10 +115,7 @@ struct TrackParams {
     int32_t path_count;
     int32_t pad_path;
     int64_t path_cap;
-    int32_t* path_cell;
-    int32_t* path_face;
-    double* path_t;
-    double* path_xyz;
+    PathRec* path_rec;
 };
 
 // Output form of a tracking kernel (template argument).

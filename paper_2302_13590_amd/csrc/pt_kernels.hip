@@ -676,11 +676,17 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
         if (!P.path_count) {
             const int64_t q = L.pq++;
             if (q >= 0 && q < L.pend) {
-                P.path_cell[q] = L.c;
-                P.path_face[q] = f;
-                P.path_t[q] = L.t;
-                global_xyz(G, L.i, L.j, L.k, (double)L.x[0], (double)L.x[1], (double)L.x[2],
-                           P.path_xyz + 3 * q);
+                // one 40-byte record: a particle's records form one contiguous stream
+                double xyz[3];
+                global_xyz(G, L.i, L.j, L.k, (double)L.x[0], (double)L.x[1], (double)L.x[2], xyz);
+                PathRec r;
+                r.t = L.t;
+                r.x = xyz[0];
+                r.y = xyz[1];
+                r.z = xyz[2];
+                r.cell = L.c;
+                r.face = f;
+                P.path_rec[q] = r;
             } else {
                 L.drop += 1u;
             }

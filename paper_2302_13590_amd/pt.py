@@ -59,7 +59,17 @@ class pt_track_opts(ctypes.Structure):
                 ("refill", ctypes.c_int32), ("steps_per_refill", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("sort", ctypes.c_int32),
                 ("path_offsets", _p), ("path_count_only", ctypes.c_int32), ("path_cap", ctypes.c_int64),
-                ("path_cell", _p), ("path_face", _p), ("path_t", _p), ("path_xyz", _p)]
+                ("path_records", _p)]
+
+
+class pt_path_record(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("x", ctypes.c_double), ("y", ctypes.c_double), ("z", ctypes.c_double),
+                ("cell", ctypes.c_int32), ("face", ctypes.c_int32)]
+
+
+# host view of pt_path_record arrays
+PATH_RECORD_DTYPE = np.dtype([("t", "<f8"), ("x", "<f8"), ("y", "<f8"), ("z", "<f8"), ("cell", "<i4"),
+                              ("face", "<i4")])
 
 
 class pt_summary(ctypes.Structure):
@@ -248,7 +258,7 @@ def make_opts(mode=PT_ENDPOINT, precision=PT_FP64, schedule=PT_SCHED_AUTO, layou
               direction=1, stop_at_sink=1, t_max=math.inf, max_steps=1 << 20, snap_times=None,
               snap_xyz=None, out_xyz=None, use_graph=0, block=0, blocks_per_cu=0, refill=0,
               steps_per_refill=0, chunk=0, sort=0, path_offsets=None, path_count_only=0, path_cap=0,
-              path_cell=None, path_face=None, path_t=None, path_xyz=None):
+              path_records=None):
     o = pt_default_opts()
     o.mode, o.precision, o.schedule, o.layout = mode, precision, schedule, layout
     o.direction, o.stop_at_sink, o.t_max, o.max_steps = direction, stop_at_sink, t_max, max_steps
@@ -263,8 +273,7 @@ def make_opts(mode=PT_ENDPOINT, precision=PT_FP64, schedule=PT_SCHED_AUTO, layou
     o.use_graph, o.block, o.blocks_per_cu, o.refill, o.steps_per_refill, o.chunk, o.sort = (
         use_graph, block, blocks_per_cu, refill, steps_per_refill, chunk, sort)
     o.path_offsets, o.path_count_only, o.path_cap = _ptr(path_offsets), path_count_only, path_cap
-    o.path_cell, o.path_face, o.path_t, o.path_xyz = (_ptr(path_cell), _ptr(path_face), _ptr(path_t),
-                                                      _ptr(path_xyz))
+    o.path_records = _ptr(path_records)
     o._keep = keep
     return o
 
@@ -313,19 +322,43 @@ def track(grids, particles: DeviceParticles, stream=None, group_offsets=None, gr
         run.release()
 
 
+def path_record_buffer(m: int, device="cuda") -> torch.Tensor:
+    """Device storage for m pt_path_record (40 bytes each) as a float64 [m, 5] tensor."""
+    return torch.empty((m, 5), dtype=torch.float64, device=device)
+
+
 @dataclasses.dataclass
 class Pathlines:
-    """Pathline records in CSR form: those of particle p are rows offsets[p]:offsets[p+1]."""
+    """Pathline records in CSR form: those of particle p are rows offsets[p]:offsets[p+1] of
+    `records` (pt_path_record: t, x, y, z, then cell and face as two int32 in column 4)."""
     offsets: torch.Tensor   # int64 [n+1]
-    cell: torch.Tensor      # int32 [m] cell left
-    face: torch.Tensor      # int32 [m] 2*axis + 1 for the high face
-    t: torch.Tensor         # float64 [m] time of the crossing
-    xyz: torch.Tensor       # float64 [m, 3] global position on the face
+    records: torch.Tensor   # float64 [m, 5]
+
+    @property
+    def t(self) -> torch.Tensor:
+        return self.records[:, 0]
+
+    @property
+    def xyz(self) -> torch.Tensor:
+        return self.records[:, 1:4]
+
+    @property
+    def cell(self) -> torch.Tensor:
+        return self.records.view(torch.int32)[:, 8]
+
+    @property
+    def face(self) -> torch.Tensor:
+        return self.records.view(torch.int32)[:, 9]
+
+    def to_numpy(self):
+        """(offsets, structured array of PATH_RECORD_DTYPE) on the host."""
+        rec = np.ascontiguousarray(self.records.cpu().numpy()).view(PATH_RECORD_DTYPE).reshape(-1)
+        return self.offsets.cpu().numpy(), rec
 
 
 def track_pathlines(grids, particles: DeviceParticles, stream=None, group_offsets=None, group_grid=None,
                     **opt):
-    """Pathline run: the count pass (offsets), device buffers of the reported size, the record pass.
+    """Pathline run: the count pass (offsets), a record buffer of the reported size, the record pass.
 
     Returns (summary of the record pass, Pathlines).  Both passes run in the library; this
     helper only allocates the output tensors between them."""
@@ -335,11 +368,7 @@ def track_pathlines(grids, particles: DeviceParticles, stream=None, group_offset
     s0 = track(grids, particles, stream=stream, group_offsets=group_offsets, group_grid=group_grid,
                path_count_only=1, **kw)
     m = s0["path_records"]
-    out = Pathlines(offsets, torch.empty(m, dtype=torch.int32, device=dev),
-                    torch.empty(m, dtype=torch.int32, device=dev),
-                    torch.empty(m, dtype=torch.float64, device=dev),
-                    torch.empty((m, 3), dtype=torch.float64, device=dev))
+    out = Pathlines(offsets, path_record_buffer(m, dev))
     s = track(grids, particles, stream=stream, group_offsets=group_offsets, group_grid=group_grid,
-              path_count_only=0, path_cap=m, path_cell=out.cell, path_face=out.face, path_t=out.t,
-              path_xyz=out.xyz, **kw)
+              path_count_only=0, path_cap=m, path_records=out.records, **kw)
     return s, out

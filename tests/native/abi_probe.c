@@ -27,8 +27,10 @@ int main(void) {
     F(pt_track_opts, use_graph); F(pt_track_opts, block); F(pt_track_opts, blocks_per_cu);
     F(pt_track_opts, refill); F(pt_track_opts, steps_per_refill); F(pt_track_opts, chunk);
     F(pt_track_opts, sort); F(pt_track_opts, path_offsets); F(pt_track_opts, path_count_only);
-    F(pt_track_opts, path_cap); F(pt_track_opts, path_cell); F(pt_track_opts, path_face);
-    F(pt_track_opts, path_t); F(pt_track_opts, path_xyz);
+    F(pt_track_opts, path_cap); F(pt_track_opts, path_records);
+    S(pt_path_record);
+    F(pt_path_record, t); F(pt_path_record, x); F(pt_path_record, y); F(pt_path_record, z);
+    F(pt_path_record, cell); F(pt_path_record, face);
     S(pt_summary);
     F(pt_summary, crossings); F(pt_summary, n_tracked); F(pt_summary, status_count);
     F(pt_summary, kernel_ms); F(pt_summary, schedule); F(pt_summary, layout); F(pt_summary, block);

@@ -56,10 +56,16 @@ def test_struct_layouts_match_binding():
         if ln:
             k, v = ln.split()
             c[k] = int(v)
-    for T in (pt.pt_grid_desc, pt.pt_particles, pt.pt_track_opts, pt.pt_summary):
+    for T in (pt.pt_grid_desc, pt.pt_particles, pt.pt_track_opts, pt.pt_summary, pt.pt_path_record):
         assert ctypes.sizeof(T) == c[T.__name__ + ".sizeof"], T.__name__
         for name, _ in T._fields_:
             assert getattr(T, name).offset == c["%s.%s" % (T.__name__, name)], (T.__name__, name)
+
+
+def test_path_record_host_dtype_matches_struct():
+    assert pt.PATH_RECORD_DTYPE.itemsize == ctypes.sizeof(pt.pt_path_record) == 40
+    for name, _ in pt.pt_path_record._fields_:
+        assert pt.PATH_RECORD_DTYPE.fields[name][1] == getattr(pt.pt_path_record, name).offset, name
 
 
 def test_version_and_defaults(lib):

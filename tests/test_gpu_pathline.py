@@ -168,26 +168,25 @@ def test_count_pass_is_dry_and_record_pass_bounded(pt):
             assert s["path_records"] == m and s["crossings"] == m
         # record pass into arrays that hold half of the records, with a guard zone after them
         cap, guard = m // 2, 4096
-        cell = torch.full((cap + guard,), -7, dtype=torch.int32, device="cuda")
-        face = torch.full((cap + guard,), -7, dtype=torch.int32, device="cuda")
-        tt = torch.full((cap + guard,), -7.0, dtype=torch.float64, device="cuda")
-        xyz = torch.full((cap + guard, 3), -7.0, dtype=torch.float64, device="cuda")
+        rec = torch.full((cap + guard, 5), -7.0, dtype=torch.float64, device="cuda")
+        pl = pt.Pathlines(offsets, rec)
         work = pt.DeviceParticles.from_numpy(p, "cuda")
-        s = pt.track(handles, work, mode=pt.PT_PATHLINE, path_offsets=offsets, path_cap=cap, path_cell=cell,
-                     path_face=face, path_t=tt, path_xyz=xyz, out_xyz=oxyz)
+        s = pt.track(handles, work, mode=pt.PT_PATHLINE, path_offsets=offsets, path_cap=cap, path_records=rec,
+                     out_xyz=oxyz)
         assert s["path_dropped"] == m - cap and s["path_records"] == cap
-        assert torch.all(cell[cap:] == -7) and torch.all(tt[cap:] == -7.0) and torch.all(xyz[cap:] == -7.0)
-        assert np.array_equal(cell[:cap].cpu().numpy(), flat["cell"][:cap])
-        assert np.array_equal(tt[:cap].cpu().numpy(), flat["t"][:cap])
+        assert torch.all(rec[cap:] == -7.0)
+        assert np.array_equal(pl.cell[:cap].cpu().numpy(), flat["cell"][:cap])
+        assert np.array_equal(pl.face[:cap].cpu().numpy(), flat["face"][:cap])
+        assert np.array_equal(pl.t[:cap].cpu().numpy(), flat["t"][:cap])
+        assert np.array_equal(pl.xyz[:cap].cpu().numpy(), flat["xyz"][:cap])
         compare(dict(work.to_numpy(), out_xyz=oxyz.cpu().numpy(), summary=s), r, label="bounded record pass",
                 spacing=(5.0, 8.0, 1.0))
         # offsets that point nowhere: nothing is written, every record is dropped
         bad = torch.full((dp.n + 1,), -5, dtype=torch.int64, device="cuda")
-        cell.fill_(-7)
+        rec.fill_(-7.0)
         work = pt.DeviceParticles.from_numpy(p, "cuda")
-        s = pt.track(handles, work, mode=pt.PT_PATHLINE, path_offsets=bad, path_cap=cap, path_cell=cell,
-                     path_face=face, path_t=tt, path_xyz=xyz)
-        assert s["path_dropped"] == m and s["path_records"] == 0 and torch.all(cell == -7)
+        s = pt.track(handles, work, mode=pt.PT_PATHLINE, path_offsets=bad, path_cap=cap, path_records=rec)
+        assert s["path_dropped"] == m and s["path_records"] == 0 and torch.all(rec == -7.0)
         # empty call: only the leading zero
         empty = C.release(rng, 0, g.nx, g.ny, g.nz)
         de = pt.DeviceParticles.from_numpy(empty, "cuda")
@@ -269,8 +268,9 @@ def test_pathline_c2_full_sampled(pt, precision):
             rows = np.concatenate([np.arange(o[q], o[q + 1]) for q in idx])
             sub = dict(offsets=np.concatenate([[0], np.cumsum(o[idx + 1] - o[idx])]).astype(np.int64))
             rows_t = torch.from_numpy(rows).cuda()
+            sel = pt.Pathlines(pl.offsets, pl.records[rows_t].contiguous())
             for k in ("cell", "face", "t", "xyz"):
-                sub[k] = getattr(pl, k)[rows_t].cpu().numpy()
+                sub[k] = getattr(sel, k).cpu().numpy()
             compare_paths(sub, offs, flat, "C2 pathline sample")
         print("C2 pathline precision %d records %d kernel ms %.3f" % (precision, m, s["kernel_ms"]))
     finally:

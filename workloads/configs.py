@@ -18,6 +18,11 @@ released near the west inlet.
       with log-uniform sizes in [1e3, 2e6], group g on realisation g mod 16.
   C5  200x200x20, sigma^2 = 2, correlation length 8; 1e6 particles in i < 5;
       positions at 100 log-spaced times from 1 d to 1e5 d.
+  TC1 the first test case's shape (Table 1): a two-dimensional aquifer of
+      1500x300 cells of 1 m, K = exp(sigma Y) with one standardised field Y
+      (correlation length 10 m) for every sigma^2 in [0.1, 5], heads 1510 m
+      (inlet) and 10 m (outlet), so a unit mean gradient; particles on the
+      line x = 10 m, uniform along y; endpoint runs to the outlet.
 
 Seeds: K field 1000*cfg + realisation, particles 2000*cfg (+ group), numpy
 PCG64.  Particles are placed by drawing a cell uniformly in the release region
@@ -106,9 +111,10 @@ class Workload:
 
 def make_grid(K: np.ndarray, dx: float, dy: float, dz: float, recharge: float = 0.0,
               source: Optional[np.ndarray] = None, sink_mask: Optional[np.ndarray] = None,
-              origin=(0.0, 0.0, 0.0), porosity: float = POROSITY, meta=None) -> Grid:
+              origin=(0.0, 0.0, 0.0), porosity: float = POROSITY, meta=None,
+              h_west: float = H_WEST, h_east: float = H_EAST) -> Grid:
     nz, ny, nx = K.shape
-    _, qx, qy, qz, rel, its = flow.solve(K, dx, dy, dz, H_WEST, H_EAST, recharge, source)
+    _, qx, qy, qz, rel, its = flow.solve(K, dx, dy, dz, h_west, h_east, recharge, source)
     flags = np.full((nz, ny, nx), FLAG_ACTIVE, dtype=np.int32)
     if sink_mask is not None:
         flags[sink_mask] |= FLAG_SINK
@@ -226,6 +232,39 @@ def c5(n: int = 1_000_000) -> Workload:
 
 
 CONFIGS = {"C1": c1, "C2": c2, "C3": c3, "C4": c4, "C5": c5}
+
+
+# ----------------------------------------------------------------------------- first test case's shape
+
+TC1_SHAPE = (1, 300, 1500)          # nz, ny, nx; cells of 1 m
+TC1_SIGMA2 = (0.1, 1.0, 2.5, 5.0)   # the paper's range of aquifer variances
+TC1_NP = (1_000, 10_000, 100_000, 1_000_000, 10_000_000)
+
+
+@functools.lru_cache(maxsize=1)
+def tc1_field() -> np.ndarray:
+    """The standardised field Y shared by every variance (seed 1000*6)."""
+    rng = np.random.Generator(np.random.PCG64(1000 * 6))
+    return kfield.gaussian_field(TC1_SHAPE, 10.0, rng)
+
+
+@functools.lru_cache(maxsize=8)
+def tc1_grid(sigma2: float) -> Grid:
+    K = np.exp(np.sqrt(sigma2) * tc1_field())
+    return make_grid(K, 1.0, 1.0, 1.0, h_west=1510.0, h_east=10.0,
+                     meta=dict(name="TC1/s2=%g" % sigma2, sigma2=sigma2))
+
+
+def tc1(n: int, sigma2: float) -> Workload:
+    """n particles on the line x = 10 m (cell column 10, xi = 0), uniform along y."""
+    g = tc1_grid(sigma2)
+    rng = np.random.Generator(np.random.PCG64(2000 * 6))
+    y = rng.random(n) * g.ny
+    j = np.minimum(np.floor(y).astype(np.int64), g.ny - 1)
+    cell = (j * g.nx + 10).astype(np.int32)
+    p = Particles(cell, np.zeros(n), np.ascontiguousarray(y - j), np.full(n, 0.5), np.zeros(n),
+                  np.zeros(n, np.int32), np.zeros(n, np.int32), np.full(n, FNV_OFFSET, dtype=np.uint64))
+    return Workload("TC1/s2=%g/n=%d" % (sigma2, n), [g], p)
 
 
 # ----------------------------------------------------------------------------- small cases

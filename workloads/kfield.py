@@ -25,6 +25,8 @@ def gaussian_field(shape, corr_len: float, rng: np.random.Generator) -> np.ndarr
     """Standardised Gaussian field Y[nz, ny, nx] with covariance exp(-|h|/corr_len)."""
     nz, ny, nx = (int(s) for s in shape)
     mz, my, mx = (_embed_size(n, corr_len) for n in (nz, ny, nx))
+    if nz == 1:
+        mz = 1      # a two-dimensional field: no embedding along the unused axis
 
     def lag(m):
         a = np.arange(m, dtype=np.float64)
