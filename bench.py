@@ -251,6 +251,49 @@ def cpu_baseline(w, n_threads):
     return res
 
 
+# launch parameters of the scheduling study (the tuned C2/C3 shapes of each kernel)
+STUDY_LAUNCH = {"static": dict(block=128), "persistent": dict(block=256, refill=8, chunk=32, steps_per_refill=2)}
+
+
+def scheduling_study(sigma2s, nps, reps):
+    """Static vs persistent kernel on the first test case's shape (Results "Thread scheduling",
+    the paper's Fig. 5 and 6 on 1-8 CPU threads): kernel time of each schedule for every
+    variance and particle count, and their ratio T_persistent / T_static (the analogue of the
+    paper's T_dyn / T_sta).  One JSON line per configuration, then a markdown table."""
+    import torch
+    from workloads import configs as C
+    rows = []
+    for s2 in sigma2s:
+        t0 = time.perf_counter()
+        C.tc1_grid(s2)
+        log("TC1 grid sigma^2=%g ready in %.1fs" % (s2, time.perf_counter() - t0))
+        for n in nps:
+            case = Case(C.tc1(n, s2))
+            row = {"sigma2": s2, "particles": n}
+            for sched in ("static", "persistent"):
+                o = case.opts("fp64", sched, **STUDY_LAUNCH[sched])
+                case.step(o)   # warm-up (graph build)
+                summ = [case.step(o) for _ in range(reps)]
+                ms = float(np.median([q["kernel_ms"] for q in summ]))
+                row[sched + "_ms"] = round(ms, 4)
+                row["crossings"] = summ[0]["crossings"]
+            nc = case.work.ncross.to(torch.float64)
+            row["crossings_per_particle_mean"] = round(float(nc.mean()), 1)
+            row["crossings_per_particle_max"] = int(nc.max())
+            row["ratio_persistent_static"] = round(row["persistent_ms"] / row["static_ms"], 4)
+            row["crossings_per_s_best"] = row["crossings"] / (1e-3 * min(row["static_ms"], row["persistent_ms"]))
+            case.release()
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+    print("\n| sigma^2 | N_p | crossings/particle (mean / max) | static ms | persistent ms | T_pers/T_stat | best crossings/s |")
+    print("|---|---|---|---|---|---|---|")
+    for r in rows:
+        print("| %g | %.0e | %.1f / %d | %.3f | %.3f | %.3f | %.3g |" % (
+            r["sigma2"], r["particles"], r["crossings_per_particle_mean"], r["crossings_per_particle_max"],
+            r["static_ms"], r["persistent_ms"], r["ratio_persistent_static"], r["crossings_per_s_best"]))
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +308,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain elementwise copy of this many bytes (HBM-counter calibration)")
+    ap.add_argument("--study", choices=["scheduling"],
+                    help="instead of the benchmark line: static vs persistent on the first test case's "
+                         "shape over variances and particle counts")
+    ap.add_argument("--study-sigma2", default="0.1,1,2.5,5")
+    ap.add_argument("--study-np", default="1e3,1e4,1e5,1e6,1e7")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -277,6 +325,9 @@ def main():
         return 1
     from paper_2302_13590_amd import pt
     pt.load_library()
+    if args.study == "scheduling":
+        return scheduling_study([float(v) for v in args.study_sigma2.split(",")],
+                                [int(float(v)) for v in args.study_np.split(",")], max(1, args.steps // 3))
 
     if args.copy_bytes > 0:
         # a plain streaming kernel of known traffic: reads and writes copy_bytes each

@@ -98,6 +98,24 @@ def test_c5_timeseries_full_sampled(pt):
     assert not np.isnan(sx[:, 0, :]).any()
 
 
+@pytest.mark.parametrize("sigma2,n", [(2.5, 100_000), (5.0, 20_000)])
+def test_tc1_shape_sampled(pt, sigma2, n):
+    """The scheduling study's workload (first test case's shape): every particle reaches the
+    outlet, in both kernels, identical to the oracle on a sample."""
+    w = C.tc1(n, sigma2)
+    p = w.particles
+    idx = sample_indices(p.n, 1500, seed=71)
+    r = O.track(w.grids[0], p.subset(idx))
+    for sched in (1, 2):
+        out = gpu_track(w.grids, p, schedule=sched, layout=2, use_graph=1)
+        _check_counters(out, p)
+        compare(out, r, idx=idx, label="TC1 s2=%g sched %d" % (sigma2, sched), spacing=(1.0, 1.0, 1.0))
+        at_outlet = (out["status"] == 1) & (out["cell"] % 1500 == 1499)
+        assert np.mean(at_outlet) > 0.999                       # displaced to the outlet
+    print("TC1 s2=%g: crossings %d, per particle mean %.1f max %d" % (
+        sigma2, out["summary"]["crossings"], out["ncross"].mean(), out["ncross"].max()))
+
+
 @pytest.mark.parametrize("cfg", ["C2", "C5"])
 def test_mixed_precision_accuracy(pt, cfg):
     """Mixed FP32/FP64 against the FP64 oracle: reported, with loose sanity bounds."""
