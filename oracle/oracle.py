@@ -65,6 +65,9 @@ def load(path: str = _LIB):
     lib.oracle_track.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Opts), ctypes.c_int64,
                                  p, p, p, p, p, p, p, p]
     lib.oracle_track.restype = ctypes.c_int
+    lib.oracle_track_transient.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int32, p, ctypes.POINTER(_Opts),
+                                           ctypes.c_int64, p, p, p, p, p, p, p, p]
+    lib.oracle_track_transient.restype = ctypes.c_int
     if path == _LIB:
         _lib = lib
     return lib
@@ -102,16 +105,35 @@ def track(grid, particles, *, direction: int = 1, t_max: float = math.inf,
     ``snap_init`` (optional [n, n_snap, 3]) is the snapshot buffer before the call,
     which matters only for resumed particles.
     """
+    return _run([grid], None, particles, direction=direction, t_max=t_max, max_steps=max_steps,
+                stop_at_sink=stop_at_sink, snap_times=snap_times, snap_init=snap_init, threads=threads,
+                path_cap=path_cap, lib=lib)
+
+
+def track_transient(grids, step_end, particles, **kw) -> Result:
+    """Transient flow: grids[s] holds the face flows of time step s up to step_end[s]
+    (strictly increasing; the last may be inf).  Same keywords as track (forward only)."""
+    se = _c(step_end, np.float64)
+    assert len(grids) == se.shape[0] >= 1
+    return _run(list(grids), se, particles, **kw)
+
+
+def _run(grid_list, step_end, particles, *, direction: int = 1, t_max: float = math.inf,
+         max_steps: int = 1 << 20, stop_at_sink: int = 1, snap_times=None, snap_init=None,
+         threads: int = 0, path_cap: int = 0, lib=None) -> Result:
     lib = lib or load()
     if threads <= 0:
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
-    g = grid
-    qx, qy, qz = _c(g.qx, np.float64), _c(g.qy, np.float64), _c(g.qz, np.float64)
-    flags = _c(g.flags, np.int32)
-    por = None if g.porosity is None else _c(g.porosity, np.float64)
-    cg = _Grid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.x0, g.y0, g.z0, qx.ctypes.data, qy.ctypes.data,
-               qz.ctypes.data, None if por is None else por.ctypes.data, g.porosity_scalar,
-               flags.ctypes.data)
+    keep = []
+    cgs = (_Grid * len(grid_list))()
+    for q, g in enumerate(grid_list):
+        qx, qy, qz = _c(g.qx, np.float64), _c(g.qy, np.float64), _c(g.qz, np.float64)
+        flags = _c(g.flags, np.int32)
+        por = None if g.porosity is None else _c(g.porosity, np.float64)
+        keep += [qx, qy, qz, flags, por]
+        cgs[q] = _Grid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.x0, g.y0, g.z0, qx.ctypes.data, qy.ctypes.data,
+                       qz.ctypes.data, None if por is None else por.ctypes.data, g.porosity_scalar,
+                       flags.ctypes.data)
     n = particles.n
     st = [_c(particles.cell, np.int32).copy(), _c(particles.xi, np.float64).copy(),
           _c(particles.eta, np.float64).copy(), _c(particles.zeta, np.float64).copy(),
@@ -136,9 +158,13 @@ def track(grid, particles, *, direction: int = 1, t_max: float = math.inf,
               None if pc is None else pc.ctypes.data, None if pf is None else pf.ctypes.data,
               None if pt is None else pt.ctypes.data, None if px is None else px.ctypes.data,
               threads)
-    rc = lib.oracle_track(ctypes.byref(cg), ctypes.byref(o), n, *(a.ctypes.data for a in st))
+    if step_end is None:
+        rc = lib.oracle_track(ctypes.byref(cgs[0]), ctypes.byref(o), n, *(a.ctypes.data for a in st))
+    else:
+        rc = lib.oracle_track_transient(cgs, len(grid_list), step_end.ctypes.data, ctypes.byref(o), n,
+                                        *(a.ctypes.data for a in st))
     if rc != 0:
-        raise ValueError("oracle_track rejected its arguments")
+        raise ValueError("the oracle rejected its arguments")
     return Result(*st, out_xyz, snaps, pc, pf, pt, px)
 
 

@@ -28,6 +28,15 @@
  *   S0 release checks; S1 cell velocities; S2 per-axis exit feasibility;
  *   S3 per-axis exit time; S4 earliest face; S5 time limit; S6 advance;
  *   S7 transfer to the neighbour and stop checks; S8 timeseries positions.
+ *
+ * Transient flow (Methods "MODPATH": the outermost loop runs over the flow
+ * model's time steps, and once the maximum time of the current flow
+ * conditions is reached the flow arrays are updated): the field of time step
+ * s holds until step_end[s].  A particle is tracked in the field of the step
+ * containing its time; when its next exit would come after the end of the
+ * step, it is advanced analytically to that end (as at the tracking time
+ * limit) and continues from the same cell and local position in the next
+ * step's field.
  * Readings where the paper is silent (tie-break, clamping, sink and time-limit
  * semantics, snapshot semantics, path hash) are stated next to each step.
  *
@@ -194,9 +203,11 @@ static void snapshots_nan(const oracle_opts* o, double* row, int32_t* next) {
     }
 }
 
-static void track_one(const oracle_grid* g, const oracle_opts* o, int64_t p, int32_t* cell_,
-                      double* xi_, double* eta_, double* zeta_, double* t_, int32_t* status_,
-                      int32_t* ncross_, uint64_t* hash_) {
+/* grids[0 .. n_steps): the field of each time step (n_steps = 1, step_end = NULL: steady). */
+static void track_one(const oracle_grid* grids, int32_t n_steps, const double* step_end,
+                      const oracle_opts* o, int64_t p, int32_t* cell_, double* xi_, double* eta_,
+                      double* zeta_, double* t_, int32_t* status_, int32_t* ncross_, uint64_t* hash_) {
+    const oracle_grid* g = grids;
     const int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
     const int64_t plane = (int64_t)g->nx * g->ny;
     double* row = (o->snap_xyz && o->n_snap > 0) ? o->snap_xyz + (int64_t)p * o->n_snap * 3 : NULL;
@@ -211,7 +222,13 @@ static void track_one(const oracle_grid* g, const oracle_opts* o, int64_t p, int
     uint64_t hash = hash_[p];
     int32_t npath = 0;
 
-    /* S0: release checks */
+    /* S0: release checks, in the field of the time step containing t (the last one
+     * when t is at or after every step end) */
+    int32_t s = 0;
+    if (step_end) {
+        while (s < n_steps - 1 && !(t < step_end[s])) ++s;
+        g = &grids[s];
+    }
     int bad = (c < 0 || c >= ncell);
     if (!bad) bad = !(g->flags[c] & CELL_ACTIVE);
     for (int a = 0; a < 3; ++a)
@@ -239,7 +256,7 @@ static void track_one(const oracle_grid* g, const oracle_opts* o, int64_t p, int
         if (row) snapshots_nan(o, row, &next);
         return;
     }
-    if (t > o->t_max) {
+    if (t > o->t_max || (step_end && t > step_end[n_steps - 1])) {
         status_[p] = ST_MAX_TIME;
         if (row) snapshots_nan(o, row, &next);
         return;
@@ -283,18 +300,42 @@ static void track_one(const oracle_grid* g, const oracle_opts* o, int64_t p, int
             }
         }
 
-        /* S5: time limit (strict: a face reached exactly at t_max is crossed) */
-        if (axis < 0 && isinf(o->t_max)) {
+        /* S5: time limit (strict: a face reached exactly at the limit is crossed).  The
+         * limit is t_max, or the end of the current time step when that comes first; at
+         * the end of a step that is not the last the particle moves on to the next step. */
+        double lim = o->t_max;
+        int next_step = 0;
+        if (step_end && step_end[s] < lim) {
+            lim = step_end[s];
+            next_step = (s + 1 < n_steps);
+        }
+        if (axis < 0 && isinf(lim)) {
             status_[p] = ST_STRANDED;
             if (row) snapshots(g, o, row, &next, c, v, loc, t, INFINITY, 1);
             break;
         }
         double t_exit = t + dt;
-        if (t_exit > o->t_max) {
-            double tau = o->t_max - t;
-            if (row) snapshots(g, o, row, &next, c, v, loc, t, o->t_max, 1);
+        if (t_exit > lim) {
+            double tau = lim - t;
+            if (row) snapshots(g, o, row, &next, c, v, loc, t, lim, 1);
             for (int a = 0; a < 3; ++a) loc[a] = advance(v[a], loc[a], tau);
-            t = o->t_max;
+            t = lim;
+            if (next_step) {
+                /* the flow arrays of the next time step; the cell must still be active
+                 * in them (else the particle stops as at an inactive cell), and a sink
+                 * there stops it as on entry */
+                ++s;
+                g = &grids[s];
+                if (!(g->flags[c] & CELL_ACTIVE)) {
+                    status_[p] = ST_INACTIVE_NEIGHBOR;
+                    break;
+                }
+                if ((g->flags[c] & CELL_SINK) && o->stop_at_sink) {
+                    status_[p] = ST_SINK;
+                    break;
+                }
+                continue;
+            }
             status_[p] = axis < 0 ? ST_STRANDED : ST_MAX_TIME;
             if (row) snapshots_nan(o, row, &next);
             break;
@@ -367,7 +408,40 @@ int oracle_track(const oracle_grid* g, const oracle_opts* o, int64_t n, int32_t*
 #pragma omp parallel for schedule(dynamic, 64) num_threads(o->n_threads > 0 ? o->n_threads : 1)
 #endif
     for (int64_t p = 0; p < n; ++p) {
-        track_one(g, o, p, cell, xi, eta, zeta, t, status, ncross, hash);
+        track_one(g, 1, NULL, o, p, cell, xi, eta, zeta, t, status, ncross, hash);
+        if (o->out_xyz) {
+            int64_t c = cell[p];
+            if (status[p] == ST_INVALID_START || c < 0 || c >= (int64_t)g->nx * g->ny * g->nz)
+                put_nan3(o->out_xyz + 3 * p);
+            else
+                global_xyz(g, c, xi[p], eta[p], zeta[p], o->out_xyz + 3 * p);
+        }
+    }
+    return 0;
+}
+
+/* Transient flow: grids[s] is the field of time step s, valid up to step_end[s] (strictly
+ * increasing, the last may be +inf); every grid has the same geometry.  Forward only. */
+int oracle_track_transient(const oracle_grid* grids, int32_t n_steps, const double* step_end,
+                           const oracle_opts* o, int64_t n, int32_t* cell, double* xi, double* eta,
+                           double* zeta, double* t, int32_t* status, int32_t* ncross, uint64_t* hash) {
+    if (!grids || !step_end || n_steps < 1 || !o || n < 0 || o->direction != 1) return -1;
+    for (int32_t q = 0; q < n_steps; ++q) {
+        const oracle_grid* a = &grids[q];
+        if (a->nx != grids[0].nx || a->ny != grids[0].ny || a->nz != grids[0].nz || a->nx <= 0 ||
+            a->ny <= 0 || a->nz <= 0)
+            return -1;
+        if (isnan(step_end[q]) || (q > 0 && !(step_end[q] > step_end[q - 1]))) return -1;
+    }
+    if (n == 0) return 0;
+    if (!cell || !xi || !eta || !zeta || !t || !status || !ncross || !hash) return -1;
+    if (o->snap_xyz && (o->n_snap < 0 || (o->n_snap > 0 && !o->snap_times))) return -1;
+    const oracle_grid* g = grids;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64) num_threads(o->n_threads > 0 ? o->n_threads : 1)
+#endif
+    for (int64_t p = 0; p < n; ++p) {
+        track_one(grids, n_steps, step_end, o, p, cell, xi, eta, zeta, t, status, ncross, hash);
         if (o->out_xyz) {
             int64_t c = cell[p];
             if (status[p] == ST_INVALID_START || c < 0 || c >= (int64_t)g->nx * g->ny * g->nz)

@@ -365,8 +365,140 @@ def pin_positions_stay_in_cell(lib):
                 assert i <= x <= i + 1 and j <= y <= j + 1, (q, p_, s, x, y)
 
 
+# ----------------------------------------------------------------------------- transient flow
+# A 40-cell channel (cells of 10 m, porosity 0.3, cross-section 100 m^2): a uniform face flow
+# q gives the velocity q / 30 m/d everywhere.  Time step s scales every flow by F[s] (the
+# third step is stagnant), so a particle's position is piecewise linear in time.
+_TS_Q = 30.0
+_TS_F = (1.0, 2.0, 0.0, 0.5)
+_TS_END = (100.0, 150.0, 180.0, math.inf)
+
+
+def _ts_grids(sink_cell=None, inactive_cell=None, at_step=1):
+    grids = []
+    for s, f in enumerate(_TS_F):
+        fl = np.full((1, 1, 40), FLAG_ACTIVE, np.int32)
+        if s >= at_step and sink_cell is not None:
+            fl[0, 0, sink_cell] |= FLAG_SINK
+        if s >= at_step and inactive_cell is not None:
+            fl[0, 0, inactive_cell] = 0
+        grids.append(_line(40, q=_TS_Q * f, flags=fl))
+    return grids
+
+
+def _ts_position(x0, t0, t):
+    """Closed form: x at time t of a particle released at x0 at time t0 (no exit)."""
+    x, a = x0, t0
+    for f, b in zip(_TS_F, _TS_END):
+        if b <= a:
+            continue
+        hi = min(b, t)
+        if hi > a:
+            x += f * (_TS_Q / 30.0) * (hi - a)
+            a = hi
+        if a >= t:
+            break
+    return x
+
+
+def _ts_exit_time(x0, t0, L=400.0):
+    a, dist = t0, L - x0
+    for f, b in zip(_TS_F, _TS_END):
+        if b <= a:
+            continue
+        v = f * _TS_Q / 30.0
+        if v > 0 and dist <= v * (b - a):
+            return a + dist / v
+        dist -= v * (b - a) if math.isfinite(b) else dist
+        a = b
+    return math.inf
+
+
+def pin_transient_closed_form(lib):
+    """Transient flow: piecewise-constant velocity in time, staged releases (one at a step
+    end exactly), a stagnant step; exit times, crossings, and positions at a time limit."""
+    grids = _ts_grids()
+    x0 = np.array([3.0, 57.5, 120.0, 260.0, 399.0, 212.5, 33.0])
+    t0 = np.array([0.0, 0.0, 130.0, 160.0, 190.0, 150.0, 100.0])
+    i0 = np.floor(x0 / 10.0).astype(int)
+    p = H.particles(i0, x0 / 10.0 - i0, 0.5, 0.5, t0)
+    r = O.track_transient(grids, _TS_END, p, lib=lib)
+    for q in range(p.n):
+        want = _ts_exit_time(x0[q], t0[q])
+        assert r.status[q] == BOUNDARY and r.ncross[q] == 40 - i0[q], (q, r.status[q], r.ncross[q])
+        assert _close(r.t[q], want, 1e-12), (q, r.t[q], want)
+    for t_max in (170.0, 150.0, 99.0):
+        r = O.track_transient(grids, _TS_END, p, t_max=t_max, lib=lib)
+        for q in range(p.n):
+            if t0[q] > t_max:
+                assert r.status[q] == MAX_TIME and r.t[q] == t0[q], q
+                continue
+            if _ts_exit_time(x0[q], t0[q]) <= t_max:
+                assert r.status[q] == BOUNDARY, (t_max, q)
+                continue
+            want = _ts_position(x0[q], t0[q], t_max)
+            # the step the particle is in when it reaches t_max: no reachable face there
+            # (the stagnant step) means STRANDED, as in a steady field
+            s_rel = min(k for k, b in enumerate(_TS_END) if t0[q] < b)   # a release at a step end
+            s_lim = max(s_rel, min(k for k, b in enumerate(_TS_END) if t_max <= b))   # is in the next
+            want_status = STRANDED if _TS_F[s_lim] == 0.0 else MAX_TIME
+            assert r.status[q] == want_status and r.t[q] == t_max, (t_max, q, r.status[q])
+            assert _close(r.out_xyz[q, 0], want, 1e-12), (t_max, q, r.out_xyz[q, 0], want)
+
+
+def pin_transient_timeseries(lib):
+    """Positions at snapshot times across time-step ends follow the piecewise closed form."""
+    grids = _ts_grids()
+    snaps = np.array([0.0, 50.0, 100.0, 125.0, 150.0, 165.0, 180.0, 250.0, 300.0])
+    p = H.particles([0, 8], [0.3, 0.25], 0.5, 0.5, [0.0, 60.0])
+    r = O.track_transient(grids, _TS_END, p, snap_times=snaps, lib=lib)
+    for q, (x0, t0) in enumerate(((3.0, 0.0), (82.5, 60.0))):
+        for k, s_ in enumerate(snaps):
+            if s_ < t0 or s_ >= r.t[q]:
+                assert np.isnan(r.snap_xyz[q, k]).all(), (q, k)
+            else:
+                assert _close(r.snap_xyz[q, k, 0], _ts_position(x0, t0, s_), 1e-12), (q, k)
+
+
+def pin_transient_switch_rules(lib):
+    """At a time-step end the particle keeps its cell and position: a cell that is a sink in
+    the next field stops it (stop_at_sink = 1) or not (0); one made inactive stops it.
+    Cell 30 (x in [300, 310)) is a sink from the second step (t >= 100) on."""
+    p = H.particles([20, 15, 2], 0.5, 0.5, 0.5)        # x0 = 205, 155, 25 m
+    r = O.track_transient(_ts_grids(sink_cell=30), _TS_END, p, lib=lib)
+    # x = 305 at t = 100: inside cell 30 when it becomes a sink
+    assert r.status[0] == SINK and r.t[0] == 100.0 and int(r.cell[0]) == 30, (r.status[0], r.t[0])
+    assert _close(r.out_xyz[0, 0], 305.0, 1e-12), r.out_xyz[0]
+    # x = 255 at t = 100, then 2 m/d: enters cell 30 at t = 122.5
+    assert r.status[1] == SINK and int(r.cell[1]) == 30 and _close(r.t[1], 122.5, 1e-12), (r.status[1], r.t[1])
+    # x = 125 at 100, 225 at 150, stagnant to 180, then 0.5 m/d: enters cell 30 at t = 330
+    assert r.status[2] == SINK and _close(r.t[2], 330.0, 1e-12), (r.status[2], r.t[2])
+    r = O.track_transient(_ts_grids(sink_cell=30), _TS_END, p, stop_at_sink=0, lib=lib)
+    assert (r.status == BOUNDARY).all()
+    # cell 12 inactive from t = 100: the third particle is inside it then
+    r = O.track_transient(_ts_grids(inactive_cell=12), _TS_END, p, lib=lib)
+    assert r.status[2] == INACTIVE_NB and r.t[2] == 100.0 and int(r.cell[2]) == 12, (r.status[2], r.t[2])
+    assert r.status[0] == BOUNDARY and r.status[1] == BOUNDARY
+
+
+def pin_transient_identical_fields(lib):
+    """Time steps that all hold the same field reproduce the steady run: same cells, path
+    hashes, crossings and statuses, times and positions equal to 1e-11."""
+    g = _rand_grid(nx=9, ny=7, nz=3, seed=21, sigma2=1.0, wells=((4, 3, -40.0),), recharge=2e-3)
+    rng = np.random.Generator(np.random.PCG64(5))
+    p = C.release(rng, 300, g.nx, g.ny, g.nz)
+    steady = O.track(g, p, max_steps=5000, lib=lib)
+    ends = np.array([7.5, 40.0, 41.0, 300.0, math.inf])
+    tr = O.track_transient([g] * ends.size, ends, p, max_steps=5000, lib=lib)
+    for name in ("status", "cell", "ncross", "path_hash"):
+        assert (getattr(tr, name) == getattr(steady, name)).all(), name
+    assert np.allclose(tr.t, steady.t, rtol=1e-11, atol=0.0)
+    assert np.allclose(tr.out_xyz, steady.out_xyz, rtol=1e-11, atol=1e-11)
+
+
 QUICK_PINS = [pin_single_cell_exit, pin_single_cell_position, pin_multi_axis_uniform,
               pin_corner_tie, pin_stops, pin_porosity_field, pin_c1_closed_form,
               pin_timeseries_c1, pin_outflow_exits, pin_reversibility, pin_resume,
-              pin_positions_stay_in_cell]
+              pin_positions_stay_in_cell, pin_transient_closed_form, pin_transient_timeseries,
+              pin_transient_switch_rules, pin_transient_identical_fields]
 ALL_PINS = QUICK_PINS + [pin_rk4]

@@ -28,7 +28,7 @@ MUTANTS = {
                        "out[1] = g->y0 + ((double)j + eta) * g->dz;"),
     "exit_time_without_log": ("dt = r * (cr_log1p(x) / x);", "dt = r;"),
     "no_ratio_branch": ("} else if (x < -0.5) {", "} else if (x < -2.0) {"),
-    "non_strict_time_limit": ("if (t_exit > o->t_max) {", "if (t_exit >= o->t_max) {"),
+    "non_strict_time_limit": ("if (t_exit > lim) {", "if (t_exit >= lim) {"),
     "scalar_porosity_only": ("double n_c = g->porosity ? g->porosity[c] : g->porosity_scalar;",
                              "double n_c = g->porosity_scalar;"),
     "wrong_hash_prime": ("0x100000001b3ULL", "0x100000001b5ULL"),
@@ -39,6 +39,17 @@ MUTANTS = {
     "no_sink_stop_on_entry": ("        if ((g->flags[c] & CELL_SINK) && o->stop_at_sink) {\n"
                               "            status_[p] = ST_SINK;\n            break;\n        }\n", ""),
     "no_clamp_high": ("    if (xn > 1.0) xn = 1.0;\n", ""),
+    "transient_field_not_switched": ("                ++s;\n                g = &grids[s];\n",
+                                     "                ++s;\n"),
+    "transient_step_end_ignored": ("if (step_end && step_end[s] < lim) {", "if (0) {"),
+    "transient_release_in_first_step": ("while (s < n_steps - 1 && !(t < step_end[s])) ++s;",
+                                        "while (0) ++s;"),
+    "transient_release_at_end_stays": ("while (s < n_steps - 1 && !(t < step_end[s])) ++s;",
+                                       "while (s < n_steps - 1 && t > step_end[s]) ++s;"),
+    "transient_no_sink_on_switch": ("                if ((g->flags[c] & CELL_SINK) && o->stop_at_sink) {\n"
+                                    "                    status_[p] = ST_SINK;\n                    break;\n"
+                                    "                }\n", ""),
+    "transient_stranded_at_step_end": ("        if (axis < 0 && isinf(lim)) {", "        if (axis < 0) {"),
 }
 
 
