@@ -68,6 +68,8 @@ def workload(name):
         return C.c4()
     if name == "C5":
         return C.c5()
+    if name == "C6":
+        return C.c6()
     raise SystemExit("unknown workload " + name)
 
 
@@ -77,6 +79,8 @@ DESCR = {
     "C3": "C3: 200x200x20 lognormal K (sigma^2=4, corr. 8 cells), 2 wells + recharge, 1e7 particles",
     "C4": "C4: 16 realisations 100x100x10 (sigma^2 ~ U[0.5,4]), 64 groups, 1.77e7 particles, batched",
     "C5": "C5: 200x200x20 lognormal K (sigma^2=2), 1e6 particles, timeseries 100 snapshots [1e6,100,3]",
+    "C6": "C6: C2's grid under transient flow (12 time steps, a well switching on and off), 1e6 particles "
+          "released in 10 stages, weak sinks pass through",
 }
 
 
@@ -104,6 +108,9 @@ class Case:
                  layout=pt.PT_LAYOUT_CELL, use_graph=1, out_xyz=self.out_xyz, t_max=self.w.t_max)
         if self.snap is not None:
             o.update(mode=pt.PT_TIMESERIES, snap_times=self.w.snap_times, snap_xyz=self.snap)
+        if self.w.tstep_end is not None:
+            o.update(tstep_end=self.w.tstep_end)
+        o.update(stop_at_sink=self.w.stop_at_sink)
         o.update(kw)
         return pt.make_opts(**o)
 

@@ -202,6 +202,20 @@ typedef struct {
     int32_t path_count_only;      /* 1: count pass, 0: record pass                               */
     int64_t path_cap;             /* records path_records can hold (record pass), >= 0           */
     pt_path_record* path_records; /* device [path_cap] (record pass; may be NULL if path_cap = 0) */
+    /* Transient flow (the paper's outermost loop over the flow model's time steps, Methods
+     * "MODPATH": once the end of the current flow conditions is reached, the flow arrays are
+     * updated).  With n_tsteps >= 1, grids[s] holds the face flows of time step s, valid until
+     * tstep_end[s]; n_grids must equal n_tsteps, every grid must have the same geometry, there
+     * are no particle groups, and direction must be +1.  A particle is tracked in the field of
+     * the step containing its time (a time equal to a step end belongs to the next step).
+     * When its next exit would come after the end of its step, it is advanced analytically to
+     * that end and continues in the next step's field from the same cell and position; if the
+     * cell is inactive there it stops (PT_INACTIVE_NEIGHBOR), if it is a sink it stops when
+     * stop_at_sink = 1 (PT_SINK).  The end of the last step acts as a time limit (PT_MAX_TIME,
+     * or PT_STRANDED when no face is reachable), like t_max. */
+    int32_t n_tsteps;             /* 0: steady flow                                              */
+    const double* tstep_end;      /* host [n_tsteps]: strictly increasing, not NaN; the last may *
+                                   * be +inf                                                    */
 } pt_track_opts;
 
 /* Fill *o with the defaults: endpoint, FP64, auto schedule and layout, forward,

@@ -292,7 +292,7 @@ hipError_t launch(const void* fn, dim3 grid, dim3 block, void* arg, hipStream_t 
 // =============================================================================================
 extern "C" {
 
-int pt_version(void) { return 101; }
+int pt_version(void) { return 102; }
 
 const char* pt_last_error(void) { return g_err.c_str(); }
 
@@ -476,7 +476,25 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     }
     const int32_t n_groups = p->n_groups;
     if (n_groups < 0) return fail(PT_ERR_INVALID_ARG, "n_groups must be >= 0");
-    if (n_grids > 1 && n_groups == 0) return fail(PT_ERR_INVALID_ARG, "several grids need particle groups");
+    const bool transient = o->n_tsteps != 0;
+    if (transient) {
+        if (o->n_tsteps < 0 || !o->tstep_end) return fail(PT_ERR_INVALID_ARG, "transient flow needs n_tsteps >= 1 and tstep_end");
+        if (o->n_tsteps != n_grids) return fail(PT_ERR_INVALID_ARG, "transient flow needs one grid per time step");
+        if (n_groups != 0) return fail(PT_ERR_UNSUPPORTED, "transient flow with particle groups");
+        if (o->direction != 1) return fail(PT_ERR_UNSUPPORTED, "transient flow is tracked forward only");
+        for (int32_t q = 0; q < o->n_tsteps; ++q) {
+            if (std::isnan(o->tstep_end[q])) return fail(PT_ERR_INVALID_ARG, "tstep_end[%d] is NaN", q);
+            if (q && !(o->tstep_end[q] > o->tstep_end[q - 1]))
+                return fail(PT_ERR_INVALID_ARG, "tstep_end must be strictly increasing");
+            const GridDev& a = grids[q]->gd;
+            const GridDev& b = grids[0]->gd;
+            if (a.nx != b.nx || a.ny != b.ny || a.nz != b.nz || a.dx != b.dx || a.dy != b.dy || a.dz != b.dz ||
+                a.x0 != b.x0 || a.y0 != b.y0 || a.z0 != b.z0)
+                return fail(PT_ERR_INVALID_ARG, "the grids of the time steps must have the same geometry");
+        }
+    } else if (n_grids > 1 && n_groups == 0) {
+        return fail(PT_ERR_INVALID_ARG, "several grids need particle groups");
+    }
     if (n_groups > 0) {
         if (!p->group_offsets || !p->group_grid)
             return fail(PT_ERR_INVALID_ARG, "group_offsets and group_grid must not be NULL");
@@ -504,11 +522,12 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
 
     // kernel choice and launch shape
     const bool batched = n_groups > 0;
+    const bool multi = batched || transient;   // the kernels that read a per-lane grid
     KernelKey key;
     key.precision = o->precision == PT_MIXED ? PMIX : P64;
     key.layout = o->layout == PT_LAYOUT_FACES ? L_FACES : L_CELL;
     key.out = ts ? O_SERIES : (path ? O_PATH : O_END);
-    key.batched = batched ? 1 : 0;
+    key.batched = multi ? 1 : 0;
     key.sched = o->schedule == PT_SCHED_STATIC ? S_STATIC : S_PERSISTENT;
     const void* fn = track_kernel(key);
     const int block = o->block ? o->block : 256;
@@ -538,13 +557,14 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     r->path_pass = path ? (path_count ? 1 : 2) : 0;
 
     // per-run tables: grid views, group table, snapshot times
-    const size_t b_grids = batched ? align_up(sizeof(GridDev) * n_grids, 256) : 0;
+    const size_t b_grids = multi ? align_up(sizeof(GridDev) * n_grids, 256) : 0;
     const size_t b_offs = batched ? align_up(sizeof(int64_t) * (n_groups + 1), 256) : 0;
     const size_t b_gg = batched ? align_up(sizeof(int32_t) * n_groups, 256) : 0;
     const size_t b_snap = ts ? align_up(sizeof(double) * o->n_snap, 256) : 0;
+    const size_t b_tstep = transient ? align_up(sizeof(double) * o->n_tsteps, 256) : 0;
     const bool sort = o->sort == PT_SORT_CELL || (o->sort == PT_SORT_AUTO && p->n >= (1 << 16));
     const size_t b_base = (sort && batched) ? align_up(sizeof(int64_t) * n_grids, 256) : 0;
-    const size_t total = b_grids + b_offs + b_gg + b_snap + b_base;
+    const size_t total = b_grids + b_offs + b_gg + b_snap + b_tstep + b_base;
     TrackParams P;
     std::memset(&P, 0, sizeof P);
     if (total) {
@@ -558,11 +578,13 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
         unsigned char* h = static_cast<unsigned char*>(r->h_tables);
         unsigned char* dd = static_cast<unsigned char*>(r->d_tables);
         size_t off = 0;
-        if (batched) {
+        if (multi) {
             GridDev* hg = reinterpret_cast<GridDev*>(h + off);
             for (int32_t q = 0; q < n_grids; ++q) hg[q] = grids[q]->gd;
             P.grids = reinterpret_cast<const GridDev*>(dd + off);
             off += b_grids;
+        }
+        if (batched) {
             std::memcpy(h + off, p->group_offsets, sizeof(int64_t) * (n_groups + 1));
             P.group_offsets = reinterpret_cast<const int64_t*>(dd + off);
             off += b_offs;
@@ -574,6 +596,11 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
             std::memcpy(h + off, o->snap_times, sizeof(double) * o->n_snap);
             P.snap_times = reinterpret_cast<const double*>(dd + off);
             off += b_snap;
+        }
+        if (transient) {
+            std::memcpy(h + off, o->tstep_end, sizeof(double) * o->n_tsteps);
+            P.tstep_end = reinterpret_cast<const double*>(dd + off);
+            off += b_tstep;
         }
         if (b_base) {
             int64_t* base = reinterpret_cast<int64_t*>(h + off);
@@ -602,6 +629,7 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     P.hash = p->path_hash;
     P.n_groups = n_groups;
     P.n_grids = n_grids;
+    P.n_tsteps = transient ? o->n_tsteps : 0;
     P.g0 = grids[0]->gd;
     P.t_max = o->t_max;
     P.max_steps = o->max_steps;

@@ -116,6 +116,11 @@ struct TrackParams {
     int32_t pad_path;
     int64_t path_cap;
     PathRec* path_rec;
+    // Transient flow (batched kernels): grids[s] is the field of time step s, valid until
+    // tstep_end[s]; the lane's grid index is its current time step.
+    int32_t n_tsteps;
+    int32_t pad_ts;
+    const double* tstep_end;
 };
 
 // Output form of a tracking kernel (template argument).

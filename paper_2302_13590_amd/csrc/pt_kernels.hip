@@ -474,6 +474,13 @@ __device__ __forceinline__ int32_t find_group(const TrackParams& P, int64_t pid)
     return lo;
 }
 
+// Time step of a particle at time t (transient flow): the first step whose end is after t.
+__device__ __forceinline__ int32_t step_of(const TrackParams& P, double t) {
+    int32_t s = 0;
+    while (s < P.n_tsteps - 1 && !(t < P.tstep_end[s])) ++s;
+    return s;
+}
+
 // Release checks (S0).  Returns 0 when the particle is to be tracked, ST_SKIP when it is
 // not tracked by this call, or a final status.
 template <int PREC, int LAYOUT, int OUT, bool BATCHED>
@@ -482,7 +489,10 @@ __device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap
     const int64_t p = L.pid;
     const int32_t st = P.status[p];
     L.g = 0;
-    if constexpr (BATCHED) L.g = P.group_grid[find_group(P, p)];
+    if constexpr (BATCHED) {
+        if (P.n_tsteps) L.g = step_of(P, P.t[p]);   // transient: the grid is the time step's
+        else L.g = P.group_grid[find_group(P, p)];
+    }
     const GridDev& G = grid_of<BATCHED>(P, L.g);
     const int64_t ncell = (int64_t)G.nx * G.ny * G.nz;
     const int32_t c = P.cell[p];
@@ -560,6 +570,9 @@ __device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap
     }
     if ((own & CF_SINK) && P.stop_at_sink) return ST_SINK;
     if (t > P.t_max) return ST_MAX_TIME;
+    if constexpr (BATCHED) {
+        if (P.n_tsteps && t > P.tstep_end[P.n_tsteps - 1]) return ST_MAX_TIME;
+    }
     return 0;
 }
 
@@ -631,18 +644,47 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
         }
     }
 
-    // time limit; a face reached exactly at t_max is crossed
-    if (axis < 0 && __builtin_isinf(P.t_max)) {
+    // time limit: t_max, or the end of the current time step when that comes first (transient
+    // flow); a face reached exactly at the limit is crossed
+    double lim = P.t_max;
+    bool next_step = false;
+    if constexpr (BATCHED) {
+        if (P.n_tsteps) {
+            const double e = P.tstep_end[L.g];
+            if (e < lim) {
+                lim = e;
+                next_step = L.g + 1 < P.n_tsteps;
+            }
+        }
+    }
+    if (axis < 0 && __builtin_isinf(lim)) {
         if constexpr (OUT == O_SERIES) write_snaps<PREC>(L, G, u1, u2, P, snap, dinf(), true);
         return ST_STRANDED;
     }
     const double t_exit = L.t + dt;
-    if (t_exit > P.t_max) {
-        const double tau = P.t_max - L.t;
-        if constexpr (OUT == O_SERIES) write_snaps<PREC>(L, G, u1, u2, P, snap, P.t_max, true);
+    if (t_exit > lim) {
+        const double tau = lim - L.t;
+        if constexpr (OUT == O_SERIES) write_snaps<PREC>(L, G, u1, u2, P, snap, lim, true);
 #pragma unroll
         for (int a = 0; a < 3; ++a) L.x[a] = adv<PREC>(u1[a], u2[a], L.x[a], tau, L.amb);
-        L.t = P.t_max;
+        L.t = lim;
+        if constexpr (BATCHED) {
+            if (next_step) {
+                // end of the time step: the next step's field, same cell and position
+                L.g += 1;
+                const GridDev& G2 = grid_of<BATCHED>(P, L.g);
+                int32_t own;
+                if constexpr (LAYOUT == L_CELL) {
+                    load_rec<PREC>(G2, L.c, P.sign, L.v1, L.v2, L.fl);
+                    own = L.fl;
+                } else {
+                    own = G2.flags[L.c];
+                }
+                if (!(own & CF_ACTIVE)) return ST_INACTIVE_NB;
+                if ((own & CF_SINK) && P.stop_at_sink) return ST_SINK;
+                return 0;
+            }
+        }
         return axis < 0 ? ST_STRANDED : ST_MAX_TIME;
     }
 

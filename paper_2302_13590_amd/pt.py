@@ -59,7 +59,7 @@ class pt_track_opts(ctypes.Structure):
                 ("refill", ctypes.c_int32), ("steps_per_refill", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("sort", ctypes.c_int32),
                 ("path_offsets", _p), ("path_count_only", ctypes.c_int32), ("path_cap", ctypes.c_int64),
-                ("path_records", _p)]
+                ("path_records", _p), ("n_tsteps", ctypes.c_int32), ("tstep_end", _p)]
 
 
 class pt_path_record(ctypes.Structure):
@@ -258,7 +258,7 @@ def make_opts(mode=PT_ENDPOINT, precision=PT_FP64, schedule=PT_SCHED_AUTO, layou
               direction=1, stop_at_sink=1, t_max=math.inf, max_steps=1 << 20, snap_times=None,
               snap_xyz=None, out_xyz=None, use_graph=0, block=0, blocks_per_cu=0, refill=0,
               steps_per_refill=0, chunk=0, sort=0, path_offsets=None, path_count_only=0, path_cap=0,
-              path_records=None):
+              path_records=None, tstep_end=None):
     o = pt_default_opts()
     o.mode, o.precision, o.schedule, o.layout = mode, precision, schedule, layout
     o.direction, o.stop_at_sink, o.t_max, o.max_steps = direction, stop_at_sink, t_max, max_steps
@@ -274,6 +274,11 @@ def make_opts(mode=PT_ENDPOINT, precision=PT_FP64, schedule=PT_SCHED_AUTO, layou
         use_graph, block, blocks_per_cu, refill, steps_per_refill, chunk, sort)
     o.path_offsets, o.path_count_only, o.path_cap = _ptr(path_offsets), path_count_only, path_cap
     o.path_records = _ptr(path_records)
+    if tstep_end is not None:
+        te = np.ascontiguousarray(tstep_end, dtype=np.float64)
+        keep.append(te)
+        o.n_tsteps = te.shape[0]
+        o.tstep_end = te.ctypes.data
     o._keep = keep
     return o
 

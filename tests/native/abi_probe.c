@@ -27,7 +27,8 @@ int main(void) {
     F(pt_track_opts, use_graph); F(pt_track_opts, block); F(pt_track_opts, blocks_per_cu);
     F(pt_track_opts, refill); F(pt_track_opts, steps_per_refill); F(pt_track_opts, chunk);
     F(pt_track_opts, sort); F(pt_track_opts, path_offsets); F(pt_track_opts, path_count_only);
-    F(pt_track_opts, path_cap); F(pt_track_opts, path_records);
+    F(pt_track_opts, path_cap); F(pt_track_opts, path_records); F(pt_track_opts, n_tsteps);
+    F(pt_track_opts, tstep_end);
     S(pt_path_record);
     F(pt_path_record, t); F(pt_path_record, x); F(pt_path_record, y); F(pt_path_record, z);
     F(pt_path_record, cell); F(pt_path_record, face);

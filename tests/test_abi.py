@@ -69,11 +69,12 @@ def test_path_record_host_dtype_matches_struct():
 
 
 def test_version_and_defaults(lib):
-    assert lib.pt_version() == 101
+    assert lib.pt_version() == 102
     o = pt.pt_default_opts()
     assert (o.mode, o.precision, o.schedule, o.layout) == (0, 0, 0, 0)
     assert o.direction == 1 and o.stop_at_sink == 1 and math.isinf(o.t_max) and o.max_steps == 1 << 20
     assert not o.path_offsets and o.path_count_only == 0 and o.path_cap == 0
+    assert o.n_tsteps == 0 and not o.tstep_end
 
 
 def _desc(g, **kw):

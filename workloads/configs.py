@@ -18,6 +18,11 @@ released near the west inlet.
       with log-uniform sizes in [1e3, 2e6], group g on realisation g mod 16.
   C5  200x200x20, sigma^2 = 2, correlation length 8; 1e6 particles in i < 5;
       positions at 100 log-spaced times from 1 d to 1e5 d.
+  C6  transient flow on C2's grid: 12 time steps (an initial steady period, ten
+      transient steps, a final steady period, as in the second test case) in
+      which a pumping-well column switches on, ramps up and off again; 1e6
+      particles in i < 10 released in 10 stages every 20 d; weak sinks (the
+      well cells) pass particles through.
   TC1 the first test case's shape (Table 1): a two-dimensional aquifer of
       1500x300 cells of 1 m, K = exp(sigma Y) with one standardised field Y
       (correlation length 10 m) for every sigma^2 in [0.1, 5], heads 1510 m
@@ -107,6 +112,8 @@ class Workload:
     snap_times: Optional[np.ndarray] = None
     group_offsets: Optional[np.ndarray] = None   # int64 [n_groups+1]
     group_grid: Optional[np.ndarray] = None      # int32 [n_groups]
+    tstep_end: Optional[np.ndarray] = None       # transient flow: grids[s] holds until tstep_end[s]
+    stop_at_sink: int = 1
 
 
 def make_grid(K: np.ndarray, dx: float, dy: float, dz: float, recharge: float = 0.0,
@@ -231,7 +238,35 @@ def c5(n: int = 1_000_000) -> Workload:
     return Workload("C5", [g], p, mode="timeseries", t_max=1e5, snap_times=c5_snap_times())
 
 
-CONFIGS = {"C1": c1, "C2": c2, "C3": c3, "C4": c4, "C5": c5}
+C6_WELL = (50, 50)                                  # (i, j) column, all layers
+C6_RATE = (0.0, 250.0, 500.0, 750.0, 1000.0, 1000.0, 750.0, 500.0, 250.0, 0.0, 0.0, 0.0)   # m^3/d
+C6_END = (50.0, 100.0, 150.0, 200.0, 300.0, 400.0, 600.0, 800.0, 1200.0, 1600.0, 2400.0, math.inf)
+
+
+@functools.lru_cache(maxsize=16)
+def c6_grid(step: int) -> Grid:
+    """C2's K field under the well rate of time step `step` (recharge 1e-4 m/d throughout);
+    each step's face flows are the steady solution of its boundary conditions."""
+    K = kfield.lognormal_k((10, 100, 100), 10.0, 1.0, 5.0, 1000 * 2)
+    rate = C6_RATE[step]
+    source = np.zeros(K.shape)
+    sink = np.zeros(K.shape, dtype=bool)
+    if rate > 0:
+        source[:, C6_WELL[1], C6_WELL[0]] = -rate / K.shape[0]
+        sink[:, C6_WELL[1], C6_WELL[0]] = True
+    return make_grid(K, 10.0, 10.0, 2.0, recharge=1e-4, source=source, sink_mask=sink,
+                     meta=dict(name="C6/step%d" % step, rate=rate))
+
+
+def c6(n: int = 1_000_000) -> Workload:
+    grids = [c6_grid(s) for s in range(len(C6_RATE))]
+    rng = np.random.Generator(np.random.PCG64(2000 * 6 + 1))
+    p = release(rng, n, 100, 100, 10, i_range=(0, 10))
+    p.t[:] = 20.0 * (np.arange(n) % 10)                  # 10 release stages every 20 d
+    return Workload("C6", grids, p, tstep_end=np.array(C6_END), stop_at_sink=0)
+
+
+CONFIGS = {"C1": c1, "C2": c2, "C3": c3, "C4": c4, "C5": c5, "C6": c6}
 
 
 # ----------------------------------------------------------------------------- first test case's shape
