@@ -53,6 +53,13 @@ class _Opts(ctypes.Structure):
                 ("path_xyz", ctypes.c_void_p), ("n_threads", ctypes.c_int32)]
 
 
+class _Quad(ctypes.Structure):
+    _fields_ = [("ncell", ctypes.c_int32), ("box", ctypes.c_void_p), ("sub_off", ctypes.c_void_p),
+                ("sub_nb", ctypes.c_void_p), ("sub_q", ctypes.c_void_p), ("sub_lo", ctypes.c_void_p),
+                ("sub_hi", ctypes.c_void_p), ("porosity", ctypes.c_void_p),
+                ("porosity_scalar", ctypes.c_double), ("flags", ctypes.c_void_p)]
+
+
 def load(path: str = _LIB):
     """Load (building if absent) an oracle shared library; returns the ctypes handle."""
     global _lib
@@ -68,6 +75,9 @@ def load(path: str = _LIB):
     lib.oracle_track_transient.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int32, p, ctypes.POINTER(_Opts),
                                            ctypes.c_int64, p, p, p, p, p, p, p, p]
     lib.oracle_track_transient.restype = ctypes.c_int
+    lib.oracle_track_quad.argtypes = [ctypes.POINTER(_Quad), ctypes.POINTER(_Opts), ctypes.c_int64,
+                                      p, p, p, p, p, p, p, p]
+    lib.oracle_track_quad.restype = ctypes.c_int
     if path == _LIB:
         _lib = lib
     return lib
@@ -118,14 +128,29 @@ def track_transient(grids, step_end, particles, **kw) -> Result:
     return _run(list(grids), se, particles, **kw)
 
 
+def track_quad(qgrid, particles, **kw) -> Result:
+    """Track through a quadtree grid (workloads.quadtree.QuadGrid); same keywords as track."""
+    return _run([qgrid], None, particles, quad=True, **kw)
+
+
 def _run(grid_list, step_end, particles, *, direction: int = 1, t_max: float = math.inf,
          max_steps: int = 1 << 20, stop_at_sink: int = 1, snap_times=None, snap_init=None,
-         threads: int = 0, path_cap: int = 0, lib=None) -> Result:
+         threads: int = 0, path_cap: int = 0, lib=None, quad: bool = False) -> Result:
     lib = lib or load()
     if threads <= 0:
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
     keep = []
     cgs = (_Grid * len(grid_list))()
+    cq = None
+    if quad:
+        g = grid_list[0]
+        arrs = [_c(g.box, np.float64), _c(g.sub_off, np.int32), _c(g.sub_nb, np.int32), _c(g.sub_q, np.float64),
+                _c(g.sub_lo, np.float64), _c(g.sub_hi, np.float64),
+                None if g.porosity is None else _c(g.porosity, np.float64), _c(g.flags, np.int32)]
+        keep += arrs
+        ptrs = [None if a is None else a.ctypes.data for a in arrs]
+        cq = _Quad(g.ncell, *ptrs[:7], g.porosity_scalar, ptrs[7])
+        grid_list = []
     for q, g in enumerate(grid_list):
         qx, qy, qz = _c(g.qx, np.float64), _c(g.qy, np.float64), _c(g.qz, np.float64)
         flags = _c(g.flags, np.int32)
@@ -158,7 +183,9 @@ def _run(grid_list, step_end, particles, *, direction: int = 1, t_max: float = m
               None if pc is None else pc.ctypes.data, None if pf is None else pf.ctypes.data,
               None if pt is None else pt.ctypes.data, None if px is None else px.ctypes.data,
               threads)
-    if step_end is None:
+    if cq is not None:
+        rc = lib.oracle_track_quad(ctypes.byref(cq), ctypes.byref(o), n, *(a.ctypes.data for a in st))
+    elif step_end is None:
         rc = lib.oracle_track(ctypes.byref(cgs[0]), ctypes.byref(o), n, *(a.ctypes.data for a in st))
     else:
         rc = lib.oracle_track_transient(cgs, len(grid_list), step_end.ctypes.data, ctypes.byref(o), n,

@@ -157,6 +157,33 @@ static double axis_exit_time(axis_vel v, double xi, double* xi_exit) {
     return dt;
 }
 
+/* S2-S4: the earliest reachable face over the three axes; exact ties go to the lowest axis.
+ * Returns the time (+INFINITY and *axis = -1 when no face can be reached). */
+static double earliest_exit(const axis_vel* v, const double* loc, int* axis, double* xe) {
+    double dt = INFINITY;
+    *axis = -1;
+    *xe = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double e = 0.0;
+        double ta = axis_exit_time(v[a], loc[a], &e);
+        if (ta < dt) {
+            dt = ta;
+            *axis = a;
+            *xe = e;
+        }
+    }
+    return dt;
+}
+
+/* Path identity: FNV-1a style over the cells left. */
+static uint64_t hash_step(uint64_t h, int64_t c) { return (h ^ (uint64_t)(uint32_t)c) * 0x100000001b3ULL; }
+
+static double cell_porosity(const double* porosity, double scalar, int64_t c) {
+    return porosity ? porosity[c] : scalar;
+}
+
+static double direction_sign(const oracle_opts* o) { return o->direction < 0 ? -1.0 : 1.0; }
+
 static void global_xyz(const oracle_grid* g, int64_t c, double xi, double eta, double zeta,
                        double* out) {
     int64_t plane = (int64_t)g->nx * g->ny;
@@ -181,19 +208,31 @@ static void put_nan3(double* p) {
  * (time t, coordinates loc) with tau = s - t.  *next is the first snapshot
  * not yet written.
  */
-static void snapshots(const oracle_grid* g, const oracle_opts* o, double* row, int32_t* next,
-                      int64_t c, const axis_vel* v, const double* loc, double t, double to,
-                      int closed) {
+typedef struct oracle_quad oracle_quad;
+static void quad_xyz(const oracle_quad* g, int64_t c, const double* loc, double* out);
+
+/* Snapshot positions in a structured grid (g) or a quadtree grid (qg, when g is NULL). */
+static void snapshots_in(const oracle_grid* g, const oracle_quad* qg, const oracle_opts* o, double* row,
+                         int32_t* next, int64_t c, const axis_vel* v, const double* loc, double t, double to,
+                         int closed) {
     while (*next < o->n_snap) {
         double s = o->snap_times[*next];
         if (closed ? !(s <= to) : !(s < to)) break;
         double tau = s - t;
-        double a = advance(v[0], loc[0], tau);
-        double b = advance(v[1], loc[1], tau);
-        double d = advance(v[2], loc[2], tau);
-        global_xyz(g, c, a, b, d, row + 3 * (int64_t)(*next));
+        double l2[3];
+        for (int a = 0; a < 3; ++a) l2[a] = advance(v[a], loc[a], tau);
+        if (g)
+            global_xyz(g, c, l2[0], l2[1], l2[2], row + 3 * (int64_t)(*next));
+        else
+            quad_xyz(qg, c, l2, row + 3 * (int64_t)(*next));
         ++*next;
     }
+}
+
+static void snapshots(const oracle_grid* g, const oracle_opts* o, double* row, int32_t* next,
+                      int64_t c, const axis_vel* v, const double* loc, double t, double to,
+                      int closed) {
+    snapshots_in(g, NULL, o, row, next, c, v, loc, t, to, closed);
 }
 
 static void snapshots_nan(const oracle_opts* o, double* row, int32_t* next) {
@@ -263,14 +302,14 @@ static void track_one(const oracle_grid* grids, int32_t n_steps, const double* s
     }
 
     const double V = (g->dx * g->dy) * g->dz;
-    const double sgn = o->direction < 0 ? -1.0 : 1.0;
+    const double sgn = direction_sign(o);
     for (;;) {
         /* S1: cell initialisation -- face flows to face velocities */
         int64_t k = c / plane;
         int64_t rem = c - k * plane;
         int64_t j = rem / g->nx;
         int64_t i = rem - j * g->nx;
-        double n_c = g->porosity ? g->porosity[c] : g->porosity_scalar;
+        double n_c = cell_porosity(g->porosity, g->porosity_scalar, c);
         double d = n_c * V;
         double qxl = g->qx[(k * g->ny + j) * (g->nx + 1) + i];
         double qxh = g->qx[(k * g->ny + j) * (g->nx + 1) + i + 1];
@@ -287,18 +326,9 @@ static void track_one(const oracle_grid* grids, int32_t n_steps, const double* s
         v[2].u2 = (sgn * qzh) / d;
 
         /* S2-S4: earliest feasible face; exact ties go to the lowest axis */
-        double dt = INFINITY;
-        int axis = -1;
-        double xe = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            double e = 0.0;
-            double ta = axis_exit_time(v[a], loc[a], &e);
-            if (ta < dt) {
-                dt = ta;
-                axis = a;
-                xe = e;
-            }
-        }
+        int axis;
+        double xe;
+        double dt = earliest_exit(v, loc, &axis, &xe);
 
         /* S5: time limit (strict: a face reached exactly at the limit is crossed).  The
          * limit is t_max, or the end of the current time step when that comes first; at
@@ -347,7 +377,7 @@ static void track_one(const oracle_grid* grids, int32_t n_steps, const double* s
             loc[a] = (a == axis) ? xe : advance(v[a], loc[a], dt);
         t = t_exit;
         ncross += 1;
-        hash = (hash ^ (uint64_t)(uint32_t)c) * 0x100000001b3ULL;
+        hash = hash_step(hash, c);
         if (o->path_cap > 0 && npath < o->path_cap) {
             int64_t q = (int64_t)p * o->path_cap + npath;
             o->path_cell[q] = (int32_t)c;
@@ -452,3 +482,258 @@ int oracle_track_transient(const oracle_grid* grids, int32_t n_steps, const doub
     }
     return 0;
 }
+
+/* ============================================================================================
+ * Quadtree (rectangular unstructured) grids.  The paper's second test case refines its grid
+ * with a quadtree (Methods "Synthetic test cases") and defers the tracking to MODPATH; the
+ * per-cell step is unchanged, only the geometry and the neighbour lookup differ.  Readings:
+ *   - a cell is a box [x_lo, x_lo + hx] x [y_lo, y_lo + hy] x [z_lo, z_lo + hz]; local
+ *     coordinates are (x - x_lo)/hx etc.;
+ *   - a face may be split into subfaces, each shared with one neighbour (or the domain
+ *     boundary); the face velocity of the linear interpolation is the face's total flow
+ *     (the sum of its subfaces' flows, in their order) over n V of the cell;
+ *   - a particle leaving through a face enters the neighbour of the subface that contains
+ *     its exit point (the first one in order when the point is on an edge between two);
+ *   - in the neighbour, the coordinate along the exit axis is that of the entry face; a
+ *     coordinate along a face axis carries over unchanged when both cells span the same
+ *     range on that axis, otherwise it is mapped through the global coordinate (and clamped
+ *     to [0, 1]).
+ * ============================================================================================ */
+struct oracle_quad {
+    int32_t ncell;
+    const double* box;        /* [ncell][6]: x_lo, y_lo, z_lo, hx, hy, hz */
+    const int32_t* sub_off;   /* [ncell*6 + 1]: subfaces of face f = 2*axis + side of cell c */
+    const int32_t* sub_nb;    /* [nsub] neighbour cell, -1 = domain boundary */
+    const double* sub_q;      /* [nsub] flow, + = +axis */
+    const double* sub_lo;     /* [nsub][2] extent in the face's tangential local coordinates */
+    const double* sub_hi;     /* [nsub][2] (x-face: eta, zeta; y-face: xi, zeta; z-face: xi, eta) */
+    const double* porosity;   /* [ncell] or NULL */
+    double porosity_scalar;
+    const int32_t* flags;     /* [ncell] */
+};
+
+static void quad_xyz(const oracle_quad* g, int64_t c, const double* loc, double* out) {
+    const double* b = g->box + 6 * c;
+    out[0] = b[0] + loc[0] * b[3];
+    out[1] = b[1] + loc[1] * b[4];
+    out[2] = b[2] + loc[2] * b[5];
+}
+
+static void quad_snapshots(const oracle_quad* g, const oracle_opts* o, double* row, int32_t* next, int64_t c,
+                           const axis_vel* v, const double* loc, double t, double to, int closed) {
+    snapshots_in(NULL, g, o, row, next, c, v, loc, t, to, closed);
+}
+
+#define QUAD_ZERO_RUN 16
+
+/* snapshots after a particle stopped on a circuit of zero-time crossings: it stays put */
+static void quad_snapshots_fixed(const oracle_quad* g, const oracle_opts* o, double* row, int32_t* next,
+                                 int64_t c, const double* loc) {
+    while (*next < o->n_snap && o->snap_times[*next] <= o->t_max) {
+        quad_xyz(g, c, loc, row + 3 * (int64_t)(*next));
+        ++*next;
+    }
+    snapshots_nan(o, row, next);
+}
+
+static void track_one_quad(const oracle_quad* g, const oracle_opts* o, int64_t p, int32_t* cell_,
+                           double* xi_, double* eta_, double* zeta_, double* t_, int32_t* status_,
+                           int32_t* ncross_, uint64_t* hash_) {
+    double* row = (o->snap_xyz && o->n_snap > 0) ? o->snap_xyz + (int64_t)p * o->n_snap * 3 : NULL;
+    int32_t st = status_[p];
+    if (st != ST_ACTIVE && st != ST_MAX_TIME) return;
+    const int fresh = (st == ST_ACTIVE);
+    int64_t c = cell_[p];
+    double loc[3] = {xi_[p], eta_[p], zeta_[p]};
+    double t = t_[p];
+    int32_t ncross = ncross_[p];
+    uint64_t hash = hash_[p];
+    int32_t npath = 0;
+    int32_t zero_run = 0;
+
+    /* S0 */
+    int bad = (c < 0 || c >= g->ncell);
+    if (!bad) bad = !(g->flags[c] & CELL_ACTIVE);
+    for (int a = 0; a < 3; ++a)
+        if (!(loc[a] >= 0.0 && loc[a] <= 1.0)) bad = 1;
+    if (!(t == t) || isinf(t)) bad = 1;
+    if (bad) {
+        status_[p] = ST_INVALID_START;
+        if (row) {
+            int32_t k0 = 0;
+            snapshots_nan(o, row, &k0);
+        }
+        return;
+    }
+    int32_t next = 0;
+    if (row) {
+        while (next < o->n_snap && o->snap_times[next] < t) {
+            if (fresh) put_nan3(row + 3 * (int64_t)next);
+            ++next;
+        }
+    }
+    if ((g->flags[c] & CELL_SINK) && o->stop_at_sink) {
+        status_[p] = ST_SINK;
+        if (row) snapshots_nan(o, row, &next);
+        return;
+    }
+    if (t > o->t_max) {
+        status_[p] = ST_MAX_TIME;
+        if (row) snapshots_nan(o, row, &next);
+        return;
+    }
+    const double sgn = direction_sign(o);
+    for (;;) {
+        /* S1: face velocities from the total flow of each face */
+        const double* b = g->box + 6 * c;
+        const double V = (b[3] * b[4]) * b[5];
+        const double n_c = cell_porosity(g->porosity, g->porosity_scalar, c);
+        const double d = n_c * V;
+        double face_u[6];
+        for (int f = 0; f < 6; ++f) {
+            double Q = 0.0;
+            for (int32_t q = g->sub_off[6 * c + f]; q < g->sub_off[6 * c + f + 1]; ++q) Q += g->sub_q[q];
+            face_u[f] = (sgn * Q) / d;
+        }
+        axis_vel v[3];
+        for (int a = 0; a < 3; ++a) {
+            v[a].u1 = face_u[2 * a];
+            v[a].u2 = face_u[2 * a + 1];
+        }
+
+        /* S2-S4 */
+        int axis;
+        double xe;
+        double dt = earliest_exit(v, loc, &axis, &xe);
+
+        /* S5 */
+        if (axis < 0 && isinf(o->t_max)) {
+            status_[p] = ST_STRANDED;
+            if (row) quad_snapshots(g, o, row, &next, c, v, loc, t, INFINITY, 1);
+            break;
+        }
+        double t_exit = t + dt;
+        if (t_exit > o->t_max) {
+            double tau = o->t_max - t;
+            if (row) quad_snapshots(g, o, row, &next, c, v, loc, t, o->t_max, 1);
+            for (int a = 0; a < 3; ++a) loc[a] = advance(v[a], loc[a], tau);
+            t = o->t_max;
+            status_[p] = axis < 0 ? ST_STRANDED : ST_MAX_TIME;
+            if (row) snapshots_nan(o, row, &next);
+            break;
+        }
+
+        /* S6 */
+        if (row) quad_snapshots(g, o, row, &next, c, v, loc, t, t_exit, 0);
+        for (int a = 0; a < 3; ++a)
+            loc[a] = (a == axis) ? xe : advance(v[a], loc[a], dt);
+        t = t_exit;
+        ncross += 1;
+        hash = hash_step(hash, c);
+        const int face = 2 * axis + (xe == 1.0 ? 1 : 0);
+        if (o->path_cap > 0 && npath < o->path_cap) {
+            int64_t q = (int64_t)p * o->path_cap + npath;
+            o->path_cell[q] = (int32_t)c;
+            o->path_face[q] = face;
+            o->path_t[q] = t;
+            quad_xyz(g, c, loc, o->path_xyz + 3 * q);
+            ++npath;
+        }
+
+        /* S7: the subface holding the exit point (the first in order when the point is on an
+         * edge between two), then the neighbour's coordinates */
+        const int ta1 = (axis == 0) ? 1 : 0;          /* the face's two tangential axes */
+        const int ta2 = (axis == 2) ? 1 : 2;
+        const int32_t q0 = g->sub_off[6 * c + face], q1 = g->sub_off[6 * c + face + 1];
+        int32_t hit = q1 - 1;
+        for (int32_t q = q0; q < q1; ++q) {
+            const double* lo = g->sub_lo + 2 * q;
+            const double* hi = g->sub_hi + 2 * q;
+            if (lo[0] <= loc[ta1] && loc[ta1] <= hi[0] && lo[1] <= loc[ta2] && loc[ta2] <= hi[1]) {
+                hit = q;
+                break;
+            }
+        }
+        const int64_t cn = (q1 > q0) ? g->sub_nb[hit] : -1;
+        if (cn < 0) {
+            status_[p] = ST_BOUNDARY;
+            break;
+        }
+        if (!(g->flags[cn] & CELL_ACTIVE)) {
+            status_[p] = ST_INACTIVE_NEIGHBOR;
+            break;
+        }
+        const double* bn = g->box + 6 * cn;
+        const int tang[2] = {ta1, ta2};
+        for (int m = 0; m < 2; ++m) {
+            const int a = tang[m];
+            if (bn[a] == b[a] && bn[3 + a] == b[3 + a]) continue;   /* same span: unchanged */
+            const double x = b[a] + loc[a] * b[3 + a];
+            double l = (x - bn[a]) / bn[3 + a];
+            if (l < 0.0) l = 0.0;
+            if (l > 1.0) l = 1.0;
+            loc[a] = l;
+        }
+        loc[axis] = 1.0 - xe;
+        c = cn;
+        if ((g->flags[c] & CELL_SINK) && o->stop_at_sink) {
+            status_[p] = ST_SINK;
+            break;
+        }
+        if (ncross >= o->max_steps) {
+            status_[p] = ST_STEP_CAP;
+            break;
+        }
+        /* The face velocities of a cell whose face is split are averages over the subfaces, so
+         * around a point where cells meet the velocities can hand a particle on in a closed
+         * circuit of zero-time crossings.  After QUAD_ZERO_RUN of them in a row it is stopped
+         * there as stranded. */
+        if (dt == 0.0) {
+            if (++zero_run >= QUAD_ZERO_RUN) {
+                status_[p] = ST_STRANDED;
+                break;
+            }
+        } else {
+            zero_run = 0;
+        }
+    }
+    int32_t fs = status_[p];
+    if (row && (fs == ST_BOUNDARY || fs == ST_SINK || fs == ST_STEP_CAP || fs == ST_INACTIVE_NEIGHBOR))
+        snapshots_nan(o, row, &next);
+    if (row && fs == ST_STRANDED && zero_run >= QUAD_ZERO_RUN) {
+        /* stranded on a circuit: the position holds for every later snapshot */
+        quad_snapshots_fixed(g, o, row, &next, c, loc);
+    }
+    cell_[p] = (int32_t)c;
+    xi_[p] = loc[0];
+    eta_[p] = loc[1];
+    zeta_[p] = loc[2];
+    t_[p] = t;
+    ncross_[p] = ncross;
+    hash_[p] = hash;
+}
+
+int oracle_track_quad(const oracle_quad* g, const oracle_opts* o, int64_t n, int32_t* cell, double* xi,
+                      double* eta, double* zeta, double* t, int32_t* status, int32_t* ncross, uint64_t* hash) {
+    if (!g || !o || n < 0 || g->ncell <= 0 || !g->box || !g->sub_off || !g->flags) return -1;
+    if (n == 0) return 0;
+    if (!cell || !xi || !eta || !zeta || !t || !status || !ncross || !hash) return -1;
+    if (o->snap_xyz && (o->n_snap < 0 || (o->n_snap > 0 && !o->snap_times))) return -1;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64) num_threads(o->n_threads > 0 ? o->n_threads : 1)
+#endif
+    for (int64_t p = 0; p < n; ++p) {
+        track_one_quad(g, o, p, cell, xi, eta, zeta, t, status, ncross, hash);
+        if (o->out_xyz) {
+            int64_t c = cell[p];
+            if (status[p] == ST_INVALID_START || c < 0 || c >= g->ncell) {
+                put_nan3(o->out_xyz + 3 * p);
+            } else {
+                const double loc[3] = {xi[p], eta[p], zeta[p]};
+                quad_xyz(g, c, loc, o->out_xyz + 3 * p);
+            }
+        }
+    }
+    return 0;
+}
+

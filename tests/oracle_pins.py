@@ -496,9 +496,117 @@ def pin_transient_identical_fields(lib):
     assert np.allclose(tr.out_xyz, steady.out_xyz, rtol=1e-11, atol=1e-11)
 
 
+# ----------------------------------------------------------------------------- quadtree grids
+
+def _quad(g, size):
+    from workloads import quadtree as QT
+    return QT.from_structured(g, size)
+
+
+def pin_quad_unrefined_matches_structured(lib):
+    """A quadtree grid without refinement is the structured grid: identical paths, states and
+    times (bitwise), global positions to 1e-13 (formed from the cell box instead of i*dx)."""
+    g = C.random_grid(9, 7, 3, 1.2, 2.0, 31, dx=4.0, dy=6.0, dz=1.5, wells=((4, 3, -25.0),), recharge=1e-3)
+    q = _quad(g, np.ones((g.ny, g.nx), np.int32))
+    rng = np.random.Generator(np.random.PCG64(31))
+    p = C.release(rng, 400, g.nx, g.ny, g.nz)
+    for kw in (dict(), dict(direction=-1), dict(t_max=37.0)):
+        a = O.track(g, p, max_steps=5000, lib=lib, **kw)
+        b = O.track_quad(q, p, max_steps=5000, lib=lib, **kw)
+        for name in ("status", "cell", "ncross", "path_hash", "xi", "eta", "zeta", "t"):
+            assert np.array_equal(getattr(a, name), getattr(b, name)), (kw, name)
+        assert np.allclose(a.out_xyz, b.out_xyz, rtol=1e-13, atol=1e-13), kw
+
+
+def _uniform_quad(vx=0.7, vy=0.3):
+    """16 x 16 fine cells of 1 m (height 2 m, porosity 0.25) with a uniform velocity (vx, vy),
+    merged into blocks of 4 / 2 / 1 cells around the point (5, 9)."""
+    from workloads import quadtree as QT
+    g = H.box_grid(16, 16, 1, 1.0, 1.0, 2.0, porosity=0.25)
+    g.qx[:] = vx * 0.25 * 2.0
+    g.qy[:] = vy * 0.25 * 2.0
+    return QT.from_structured(g, QT.block_sizes(16, 16, [(5, 9)], r1=1.5, r2=4.0))
+
+
+def pin_quad_uniform_flow_line(lib):
+    """Uniform flow through a refined quadtree: straight-line motion; the exit time, the final
+    position and every crossing (time and position) follow the closed form, and each crossing
+    lies on the boundary of the cell it leaves."""
+    vx, vy = 0.7, 0.3
+    q = _uniform_quad(vx, vy)
+    from workloads import quadtree as QT
+    rng = np.random.Generator(np.random.PCG64(9))
+    p = QT.release(q, rng, 300)
+    x0 = q.box[p.cell, 0] + p.xi * q.box[p.cell, 3]
+    y0 = q.box[p.cell, 1] + p.eta * q.box[p.cell, 4]
+    r = O.track_quad(q, p, path_cap=64, lib=lib)
+    t_exit = np.minimum((16.0 - x0) / vx, (16.0 - y0) / vy)
+    assert (r.status == BOUNDARY).all()
+    assert np.allclose(r.t, t_exit, rtol=1e-12, atol=1e-12)
+    assert np.allclose(r.out_xyz[:, 0], x0 + vx * r.t, rtol=0, atol=1e-11)
+    assert np.allclose(r.out_xyz[:, 1], y0 + vy * r.t, rtol=0, atol=1e-11)
+    for k in range(p.n):
+        for s_ in range(r.ncross[k]):
+            c, tt, xyz = int(r.path_cell[k, s_]), r.path_t[k, s_], r.path_xyz[k, s_]
+            assert abs(xyz[0] - (x0[k] + vx * tt)) <= 1e-11 and abs(xyz[1] - (y0[k] + vy * tt)) <= 1e-11, (k, s_)
+            b = q.box[c]
+            on_x = min(abs(xyz[0] - b[0]), abs(xyz[0] - b[0] - b[3])) <= 1e-12
+            on_y = min(abs(xyz[1] - b[1]), abs(xyz[1] - b[1] - b[4])) <= 1e-12
+            inside = (b[0] - 1e-12 <= xyz[0] <= b[0] + b[3] + 1e-12) and (b[1] - 1e-12 <= xyz[1] <= b[1] + b[4] + 1e-12)
+            assert inside and (on_x or on_y), (k, s_, c, xyz, b)
+
+
+def pin_quad_paths_connect(lib):
+    """On a heterogeneous refined grid with a well: each crossing point lies on a face of the
+    cell left and in the closed box of the next cell of the path (neighbour lookup and the
+    coordinate mapping agree with the geometry)."""
+    from workloads import quadtree as QT
+    K = np.exp(np.sqrt(1.5) * np.random.Generator(np.random.PCG64(77)).standard_normal((2, 32, 32)))
+    src = np.zeros(K.shape)
+    src[1, 13, 18] = -2.0
+    sink = src < 0
+    g = C.make_grid(K, 2.0, 3.0, 1.0, recharge=1e-3, source=src, sink_mask=sink)
+    q = QT.from_structured(g, QT.block_sizes(32, 32, [(18, 13)], r1=3.0, r2=8.0))
+    assert q.cells[:, 2].min() == 1 and q.cells[:, 2].max() == 4
+    p = QT.release(q, np.random.Generator(np.random.PCG64(78)), 500)
+    r = O.track_quad(q, p, path_cap=512, max_steps=512, lib=lib)
+    assert (r.ncross < 512).all()
+    for k in range(p.n):
+        n = int(r.ncross[k])
+        cells = list(r.path_cell[k, :n]) + [int(r.cell[k])]
+        for s_ in range(n):
+            xyz = r.path_xyz[k, s_]
+            a, b = q.box[cells[s_]], q.box[cells[s_ + 1]]
+            f = int(r.path_face[k, s_])
+            ax, side = f // 2, f % 2
+            assert abs(xyz[ax] - (a[ax] + side * a[3 + ax])) <= 1e-12 * (1 + abs(xyz[ax])), (k, s_)
+            if s_ + 1 < n or r.status[k] != BOUNDARY:
+                for m in range(3):
+                    assert b[m] - 1e-9 <= xyz[m] <= b[m] + b[3 + m] + 1e-9, (k, s_, m, xyz, b)
+
+
+def pin_quad_zero_time_circuit(lib):
+    """Four cells whose face flows circulate around their shared corner: a particle on the
+    corner is handed round with zero-time crossings and is stopped there as stranded after 16;
+    particles elsewhere circle the corner with finite times until the step cap."""
+    g = H.box_grid(2, 2, 1, 1.0, 1.0, 1.0, porosity=0.5)
+    g.qx[0, 0, 1] = 1.0      # (0,0) -> (1,0)
+    g.qy[0, 1, 1] = 1.0      # (1,0) -> (1,1)
+    g.qx[0, 1, 1] = -1.0     # (1,1) -> (0,1)
+    g.qy[0, 1, 0] = -1.0     # (0,1) -> (0,0)
+    q = _quad(g, np.ones((2, 2), np.int32))
+    p = H.particles([0, 0], [1.0, 0.3], [1.0, 0.6], 0.5)
+    r = O.track_quad(q, p, max_steps=100, lib=lib)
+    assert r.status[0] == STRANDED and r.ncross[0] == 16 and r.t[0] == 0.0, (r.status[0], r.ncross[0], r.t[0])
+    assert np.array_equal(r.out_xyz[0], [1.0, 1.0, 0.5])
+    assert r.status[1] == STEP_CAP and r.ncross[1] == 100
+
+
 QUICK_PINS = [pin_single_cell_exit, pin_single_cell_position, pin_multi_axis_uniform,
               pin_corner_tie, pin_stops, pin_porosity_field, pin_c1_closed_form,
               pin_timeseries_c1, pin_outflow_exits, pin_reversibility, pin_resume,
               pin_positions_stay_in_cell, pin_transient_closed_form, pin_transient_timeseries,
-              pin_transient_switch_rules, pin_transient_identical_fields]
+              pin_transient_switch_rules, pin_transient_identical_fields,
+              pin_quad_unrefined_matches_structured, pin_quad_uniform_flow_line, pin_quad_paths_connect,
+              pin_quad_zero_time_circuit]
 ALL_PINS = QUICK_PINS + [pin_rk4]

@@ -22,22 +22,26 @@ MUTANTS = {
     "wrong_z_high_face": ("double qzh = g->qz[((k + 1) * g->ny + j) * g->nx + i];",
                           "double qzh = g->qz[(k * g->ny + j) * g->nx + i];"),
     "tie_to_last_axis": ("if (ta < dt) {", "if (ta <= dt) {"),
-    "ignore_direction": ("const double sgn = o->direction < 0 ? -1.0 : 1.0;", "const double sgn = 1.0;"),
-    "no_flip_on_transfer": ("loc[axis] = 1.0 - xe;", "loc[axis] = xe;"),
+    "ignore_direction": ("return o->direction < 0 ? -1.0 : 1.0;", "return 1.0;"),
+    "no_flip_on_transfer": ("        c = cn;\n        loc[axis] = 1.0 - xe;", "        c = cn;\n        loc[axis] = xe;"),
+    "quad_no_flip_on_transfer": ("        loc[axis] = 1.0 - xe;\n        c = cn;", "        loc[axis] = xe;\n        c = cn;"),
     "y_scaled_by_dz": ("out[1] = g->y0 + ((double)j + eta) * g->dy;",
                        "out[1] = g->y0 + ((double)j + eta) * g->dz;"),
     "exit_time_without_log": ("dt = r * (cr_log1p(x) / x);", "dt = r;"),
     "no_ratio_branch": ("} else if (x < -0.5) {", "} else if (x < -2.0) {"),
     "non_strict_time_limit": ("if (t_exit > lim) {", "if (t_exit >= lim) {"),
-    "scalar_porosity_only": ("double n_c = g->porosity ? g->porosity[c] : g->porosity_scalar;",
-                             "double n_c = g->porosity_scalar;"),
+    "scalar_porosity_only": ("return porosity ? porosity[c] : scalar;", "return scalar;"),
     "wrong_hash_prime": ("0x100000001b3ULL", "0x100000001b5ULL"),
     "transposed_neighbour": ("int64_t cn = (kk * g->ny + jj) * g->nx + ii;",
                              "int64_t cn = (kk * g->nx + jj) * g->ny + ii;"),
     "advance_without_exp": ("double psi = (y == 0.0) ? 1.0 : cr_expm1(y) / y;", "double psi = 1.0;"),
     "snapshot_from_zero": ("double tau = s - t;", "double tau = s;"),
-    "no_sink_stop_on_entry": ("        if ((g->flags[c] & CELL_SINK) && o->stop_at_sink) {\n"
-                              "            status_[p] = ST_SINK;\n            break;\n        }\n", ""),
+    "no_sink_stop_on_entry": ("        loc[axis] = 1.0 - xe;\n        if ((g->flags[c] & CELL_SINK) && o->stop_at_sink) {\n"
+                              "            status_[p] = ST_SINK;\n            break;\n        }\n",
+                              "        loc[axis] = 1.0 - xe;\n"),
+    "quad_no_sink_stop_on_entry": ("        c = cn;\n        if ((g->flags[c] & CELL_SINK) && o->stop_at_sink) {\n"
+                                   "            status_[p] = ST_SINK;\n            break;\n        }\n",
+                                   "        c = cn;\n"),
     "no_clamp_high": ("    if (xn > 1.0) xn = 1.0;\n", ""),
     "transient_field_not_switched": ("                ++s;\n                g = &grids[s];\n",
                                      "                ++s;\n"),
@@ -50,6 +54,17 @@ MUTANTS = {
                                     "                    status_[p] = ST_SINK;\n                    break;\n"
                                     "                }\n", ""),
     "transient_stranded_at_step_end": ("        if (axis < 0 && isinf(lim)) {", "        if (axis < 0) {"),
+    "quad_always_first_subface": ("            if (lo[0] <= loc[ta1] && loc[ta1] <= hi[0] && lo[1] <= loc[ta2] && loc[ta2] <= hi[1]) {",
+                                  "            if (1) {"),
+    "quad_face_flow_first_subface": ("for (int32_t q = g->sub_off[6 * c + f]; q < g->sub_off[6 * c + f + 1]; ++q) Q += g->sub_q[q];",
+                                     "Q = g->sub_q[g->sub_off[6 * c + f]];"),
+    "quad_tangent_never_mapped": ("            if (bn[a] == b[a] && bn[3 + a] == b[3 + a]) continue;   /* same span: unchanged */",
+                                  "            continue;"),
+    "quad_tangent_always_mapped": ("            if (bn[a] == b[a] && bn[3 + a] == b[3 + a]) continue;   /* same span: unchanged */",
+                                   ""),
+    "quad_volume_square": ("const double V = (b[3] * b[4]) * b[5];", "const double V = (b[3] * b[3]) * b[5];"),
+    "quad_no_circuit_guard": ("            if (++zero_run >= QUAD_ZERO_RUN) {", "            if (0) {"),
+    "quad_position_from_wrong_extent": ("    out[1] = b[1] + loc[1] * b[4];", "    out[1] = b[1] + loc[1] * b[3];"),
 }
 
 
