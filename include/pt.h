@@ -123,6 +123,45 @@ typedef struct {
  */
 int pt_load_grid(const pt_grid_desc* desc, void* hip_stream, pt_grid** out);
 
+/* ---- quadtree grid ---------------------------------------------------------------------- */
+/*
+ * A rectangular unstructured (quadtree) grid: the paper's second test case refines its grid
+ * with a quadtree (Methods "Synthetic test cases"; "Grid complexity" in Results).  Cells are
+ * boxes; a face f = 2*axis + side (side 1 = high face) may be split into subfaces, each shared
+ * with one neighbour or the domain boundary, listed in order.  Tracking in such a cell is the
+ * structured step with the face's total flow (its subfaces' flows summed in order) as the flow
+ * of that face.  A particle leaving through a face enters the neighbour of the subface holding
+ * its exit point (the first in order when the point is on an edge between two); in the
+ * neighbour, a face coordinate carries over when both cells span the same range on that axis,
+ * otherwise it is mapped through the global coordinate and clamped to [0, 1].  Because the
+ * velocity of a split face is an average, face velocities can circulate around a point where
+ * cells meet; a particle handed round such a point in 16 zero-time crossings in a row stops
+ * there as PT_STRANDED.  Quadtree grids are tracked in FP64, one grid per call, steady flow,
+ * with the packed layout (PT_LAYOUT_AUTO or PT_LAYOUT_CELL); every output mode is supported.
+ */
+typedef struct {
+    int32_t ncell;                /* cells, >= 1                                                 */
+    int32_t nsub;                 /* subfaces, >= 0                                              */
+    const double* box;            /* [ncell][6] x_lo, y_lo, z_lo, hx, hy, hz (h finite, > 0)     */
+    const int32_t* sub_off;       /* [ncell*6 + 1]: the subfaces of face f of cell c are          *
+                                   * sub_off[6c+f] .. sub_off[6c+f+1]-1; non-decreasing from 0   *
+                                   * to nsub, at most 31 per face                                */
+    const int32_t* sub_nb;        /* [nsub] neighbour cell, or -1 for the domain boundary        */
+    const double* sub_q;          /* [nsub] flow through the subface, + = +axis                  */
+    const double* sub_lo;         /* [nsub][2] extent of the subface in the face's two           */
+    const double* sub_hi;         /* [nsub][2] tangential local coordinates (x-face: eta, zeta;  *
+                                   * y-face: xi, zeta; z-face: xi, eta), 0 <= lo <= hi <= 1      */
+    const double* porosity;       /* [ncell] in (0, inf), or NULL -> porosity_scalar             */
+    double porosity_scalar;
+    const int32_t* flags;         /* [ncell] PT_CELL_* bits; NULL -> every cell active           */
+    int32_t mem;                  /* PT_MEM_HOST only (the description is checked on the host)   */
+    double balance_tol;           /* as in pt_grid_desc                                          */
+} pt_quad_desc;
+
+/* Copy a quadtree grid to the device and build its records; validation and ownership as in
+ * pt_load_grid (PT_ERR_UNSUPPORTED for device-resident descriptions). */
+int pt_load_quad_grid(const pt_quad_desc* desc, void* hip_stream, pt_grid** out);
+
 /* ---- particles -------------------------------------------------------------------------- */
 typedef struct {
     int64_t n;                    /* number of particles, 0 <= n < 2^31 (0: an empty run)         */

@@ -105,6 +105,7 @@ bool is_fin(double v) { return std::isfinite(v); }
 struct pt_grid {
     uint32_t magic;
     int device;
+    bool quad = false;   // a quadtree grid (QuadRec records, boxes, subfaces)
     GridDev gd;
     std::vector<void*> allocs;
 };
@@ -416,6 +417,129 @@ int pt_load_grid(const pt_grid_desc* d, void* hip_stream, pt_grid** out) {
     return PT_OK;
 }
 
+int pt_load_quad_grid(const pt_quad_desc* d, void* hip_stream, pt_grid** out) {
+    g_err.clear();
+    if (!out) return fail(PT_ERR_INVALID_ARG, "out must not be NULL");
+    *out = nullptr;
+    if (!d) return fail(PT_ERR_INVALID_ARG, "desc must not be NULL");
+    if (d->mem != PT_MEM_HOST) return fail(PT_ERR_UNSUPPORTED, "quadtree grids are loaded from host memory");
+    if (d->ncell < 1 || d->nsub < 0) return fail(PT_ERR_INVALID_ARG, "ncell must be >= 1 and nsub >= 0");
+    if (!d->box || !d->sub_off) return fail(PT_ERR_INVALID_ARG, "box and sub_off must not be NULL");
+    if (d->nsub > 0 && (!d->sub_nb || !d->sub_q || !d->sub_lo || !d->sub_hi))
+        return fail(PT_ERR_INVALID_ARG, "the subface arrays must not be NULL");
+    if (!d->porosity && (!(d->porosity_scalar > 0) || !is_fin(d->porosity_scalar)))
+        return fail(PT_ERR_INVALID_ARG, "porosity_scalar must be finite and > 0 when porosity is NULL");
+    if (std::isnan(d->balance_tol)) return fail(PT_ERR_INVALID_ARG, "balance_tol is NaN");
+    const int64_t ncell = d->ncell, nsub = d->nsub;
+    if (d->sub_off[0] != 0 || d->sub_off[6 * ncell] != nsub)
+        return fail(PT_ERR_INVALID_ARG, "sub_off must start at 0 and end at nsub");
+    for (int64_t q = 0; q < 6 * ncell; ++q) {
+        const int64_t cnt = (int64_t)d->sub_off[q + 1] - d->sub_off[q];
+        if (cnt < 0) return fail(PT_ERR_INVALID_ARG, "sub_off must be non-decreasing");
+        if (cnt > kMaxSubPerFace) return fail(PT_ERR_UNSUPPORTED, "more than 31 subfaces on one face");
+    }
+    for (int64_t c = 0; c < ncell; ++c)
+        for (int a = 0; a < 3; ++a) {
+            const double lo = d->box[6 * c + a], h = d->box[6 * c + 3 + a];
+            if (!is_fin(lo) || !is_fin(h) || !(h > 0)) return fail(PT_ERR_INVALID_ARG, "box of cell %lld", (long long)c);
+        }
+    std::vector<double4> rect((size_t)std::max<int64_t>(1, nsub));
+    for (int64_t q = 0; q < nsub; ++q) {
+        if (d->sub_nb[q] < -1 || d->sub_nb[q] >= d->ncell)
+            return fail(PT_ERR_INVALID_ARG, "sub_nb[%lld] out of range", (long long)q);
+        const double lu = d->sub_lo[2 * q], lv = d->sub_lo[2 * q + 1];
+        const double hu = d->sub_hi[2 * q], hv = d->sub_hi[2 * q + 1];
+        if (!(0.0 <= lu && lu <= hu && hu <= 1.0) || !(0.0 <= lv && lv <= hv && hv <= 1.0))
+            return fail(PT_ERR_INVALID_ARG, "subface %lld extent must satisfy 0 <= lo <= hi <= 1", (long long)q);
+        rect[q] = make_double4(lu, lv, hu, hv);
+    }
+    int dev = 0;
+    int rc = current_device(&dev, nullptr);
+    if (rc != PT_OK) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    pt_grid* g = new pt_grid();
+    g->magic = kGridMagic;
+    g->device = dev;
+    g->quad = true;
+    auto alloc = [&](size_t bytes, void** ptr) -> hipError_t {
+        hipError_t e = hipMalloc(ptr, bytes);
+        if (e == hipSuccess) g->allocs.push_back(*ptr);
+        return e;
+    };
+    const size_t n_sub = (size_t)std::max<int64_t>(1, nsub);
+    void *box, *off, *nb, *sq, *sr, *por = nullptr, *flags, *rec, *err;
+    hipError_t e = alloc(sizeof(QuadBox) * ncell, &box);
+    if (e == hipSuccess) e = alloc(sizeof(int32_t) * (6 * ncell + 1), &off);
+    if (e == hipSuccess) e = alloc(sizeof(int32_t) * n_sub, &nb);
+    if (e == hipSuccess) e = alloc(sizeof(double) * n_sub, &sq);
+    if (e == hipSuccess) e = alloc(sizeof(double4) * n_sub, &sr);
+    if (e == hipSuccess && d->porosity) e = alloc(sizeof(double) * ncell, &por);
+    if (e == hipSuccess) e = alloc(sizeof(int32_t) * ncell, &flags);
+    if (e == hipSuccess) e = alloc(sizeof(QuadRec) * ncell, &rec);
+    if (e == hipSuccess) e = alloc(4 * sizeof(int), &err);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_grid(g);
+        return fail(hip_code(e), "grid allocation failed: %s", hipGetErrorString(e));
+    }
+    std::vector<int32_t> ones;
+    if (!d->flags) ones.assign((size_t)ncell, PT_CELL_ACTIVE);
+    const hipMemcpyKind h2d = hipMemcpyHostToDevice;
+    e = hipMemcpyAsync(box, d->box, sizeof(QuadBox) * ncell, h2d, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(off, d->sub_off, sizeof(int32_t) * (6 * ncell + 1), h2d, s);
+    if (e == hipSuccess && nsub) e = hipMemcpyAsync(nb, d->sub_nb, sizeof(int32_t) * nsub, h2d, s);
+    if (e == hipSuccess && nsub) e = hipMemcpyAsync(sq, d->sub_q, sizeof(double) * nsub, h2d, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(sr, rect.data(), sizeof(double4) * n_sub, h2d, s);
+    if (e == hipSuccess && d->porosity) e = hipMemcpyAsync(por, d->porosity, sizeof(double) * ncell, h2d, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(flags, d->flags ? d->flags : ones.data(), sizeof(int32_t) * ncell, h2d, s);
+    if (e == hipSuccess) e = hipMemsetAsync(err, 0, 4 * sizeof(int), s);
+    BuildQuadParams B;
+    std::memset(&B, 0, sizeof B);
+    B.ncell = ncell;
+    B.box = static_cast<const QuadBox*>(box);
+    B.sub_off = static_cast<const int32_t*>(off);
+    B.sub_q = static_cast<const double*>(sq);
+    B.por = static_cast<const double*>(por);
+    B.por_scalar = d->porosity ? 0.0 : d->porosity_scalar;
+    B.flags = static_cast<const int32_t*>(flags);
+    B.rec = static_cast<QuadRec*>(rec);
+    B.balance_tol = d->balance_tol;
+    B.err = static_cast<int*>(err);
+    if (e == hipSuccess)
+        e = launch(build_quad_kernel(), dim3((unsigned)((ncell + 255) / 256)), dim3(256), &B, s);
+    int herr[4] = {0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(herr, err, sizeof herr, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_grid(g);
+        return fail(hip_code(e), "grid upload failed: %s", hipGetErrorString(e));
+    }
+    if (herr[0] || herr[1] || herr[2] || herr[3]) {
+        free_grid(g);
+        if (herr[0]) return fail(PT_ERR_INVALID_ARG, "a subface flow is not finite");
+        if (herr[1]) return fail(PT_ERR_INVALID_ARG, "a porosity is not finite and > 0");
+        if (herr[2]) return fail(PT_ERR_INVALID_ARG, "a cell flag has unknown bits");
+        return fail(PT_ERR_UNBALANCED, "a cell's face flows do not balance within balance_tol");
+    }
+    GridDev& gd = g->gd;
+    std::memset(&gd, 0, sizeof gd);
+    gd.rec64 = reinterpret_cast<const CellRec64*>(rec);   // QuadRec shares the record prefix
+    gd.por = static_cast<double*>(por);
+    gd.flags = static_cast<int32_t*>(flags);
+    gd.por_scalar = B.por_scalar;
+    gd.nx = d->ncell;
+    gd.ny = 1;
+    gd.nz = 1;
+    gd.qbox = static_cast<const QuadBox*>(box);
+    gd.sub_nb = static_cast<const int32_t*>(nb);
+    gd.sub_rect = static_cast<const double4*>(sr);
+    add_live(g);
+    *out = g;
+    return PT_OK;
+}
+
 int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p, const pt_track_opts* o,
              void* hip_stream, pt_run** out) {
     g_err.clear();
@@ -477,6 +601,14 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     const int32_t n_groups = p->n_groups;
     if (n_groups < 0) return fail(PT_ERR_INVALID_ARG, "n_groups must be >= 0");
     const bool transient = o->n_tsteps != 0;
+    bool quad = false;
+    for (int32_t q = 0; q < n_grids; ++q) quad = quad || grids[q]->quad;
+    if (quad) {
+        if (n_grids != 1 || n_groups != 0 || transient)
+            return fail(PT_ERR_UNSUPPORTED, "a quadtree grid is tracked alone (one grid, no groups, steady flow)");
+        if (o->precision != PT_FP64) return fail(PT_ERR_UNSUPPORTED, "quadtree grids are tracked in FP64");
+        if (o->layout == PT_LAYOUT_FACES) return fail(PT_ERR_UNSUPPORTED, "quadtree grids use the packed layout");
+    }
     if (transient) {
         if (o->n_tsteps < 0 || !o->tstep_end) return fail(PT_ERR_INVALID_ARG, "transient flow needs n_tsteps >= 1 and tstep_end");
         if (o->n_tsteps != n_grids) return fail(PT_ERR_INVALID_ARG, "transient flow needs one grid per time step");
@@ -525,7 +657,7 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     const bool multi = batched || transient;   // the kernels that read a per-lane grid
     KernelKey key;
     key.precision = o->precision == PT_MIXED ? PMIX : P64;
-    key.layout = o->layout == PT_LAYOUT_FACES ? L_FACES : L_CELL;
+    key.layout = quad ? L_QUAD : (o->layout == PT_LAYOUT_FACES ? L_FACES : L_CELL);
     key.out = ts ? O_SERIES : (path ? O_PATH : O_END);
     key.batched = multi ? 1 : 0;
     key.sched = o->schedule == PT_SCHED_STATIC ? S_STATIC : S_PERSISTENT;
@@ -551,7 +683,7 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
         if (need < grid) grid = (int)std::max<int64_t>(1, need);
     }
     r->sched = key.sched == S_STATIC ? PT_SCHED_STATIC : PT_SCHED_PERSISTENT;
-    r->layout = key.layout == L_FACES ? PT_LAYOUT_FACES : PT_LAYOUT_CELL;
+    r->layout = key.layout == L_FACES ? PT_LAYOUT_FACES : PT_LAYOUT_CELL;   // quadtree: its packed records
     r->block = block;
     r->grid = grid;
     r->path_pass = path ? (path_count ? 1 : 2) : 0;

@@ -39,6 +39,24 @@ struct alignas(32) CellRec32 {
 };
 static_assert(sizeof(CellRec32) == 32, "CellRec32 must be 32 bytes");
 
+// Quadtree grids: the same 64-byte record (u = total face flow / (n V), own flags in the flag
+// word), with the cell's first subface and the subface count of each face (5 bits per face,
+// face f at bit 5f) in the padding.  A subface's extent in the face's two tangential local
+// coordinates is {lo_u, lo_v, hi_u, hi_v}.
+struct alignas(64) QuadRec {
+    double u[6];
+    int32_t flags;
+    int32_t sub_base;
+    uint32_t counts;
+    int32_t pad0;
+};
+static_assert(sizeof(QuadRec) == 64, "QuadRec must be 64 bytes");
+constexpr int kMaxSubPerFace = 31;
+struct QuadBox {
+    double lo[3];   // x_lo, y_lo, z_lo
+    double h[3];    // hx, hy, hz
+};
+
 // One flow field as the kernels see it.
 struct GridDev {
     const CellRec64* rec64;
@@ -52,6 +70,10 @@ struct GridDev {
     double dx, dy, dz, x0, y0, z0;
     double V;               // (dx*dy)*dz
     int32_t nx, ny, nz, pad;
+    // quadtree grids (nx = number of cells, ny = nz = 1; rec64 points at QuadRec records)
+    const QuadBox* qbox;
+    const int32_t* sub_nb;
+    const double4* sub_rect;
 };
 
 constexpr int kXcd = 8;   // accelerator complex dies; workgroup b runs on die b mod 8
@@ -157,7 +179,7 @@ struct SortParams {
 constexpr int kMaxBuckets = 1 << 16;
 
 enum Precision { P64 = 0, PMIX = 1 };
-enum Layout { L_FACES = 1, L_CELL = 2 };
+enum Layout { L_FACES = 1, L_CELL = 2, L_QUAD = 3 };
 enum Sched { S_STATIC = 1, S_PERSISTENT = 2 };
 
 struct KernelKey {
@@ -175,6 +197,7 @@ const void* scan_tiles_kernel();
 const void* scan_partials_kernel();
 const void* scan_add_kernel();
 const void* build_kernel();
+const void* build_quad_kernel();
 
 // Grid build kernel arguments.
 struct BuildParams {
@@ -183,6 +206,20 @@ struct BuildParams {
     CellRec32* rec32;
     double balance_tol;
     int* err;               // [4]: non-finite flow, bad porosity, bad flags, unbalanced
+};
+
+// Quadtree grid build kernel arguments.
+struct BuildQuadParams {
+    int64_t ncell;
+    const QuadBox* box;
+    const int32_t* sub_off;     // [ncell*6 + 1]
+    const double* sub_q;
+    const double* por;          // nullptr -> por_scalar
+    double por_scalar;
+    const int32_t* flags;       // nullptr -> all active
+    QuadRec* rec;
+    double balance_tol;
+    int* err;                   // [4]: non-finite flow, bad porosity, bad flags, unbalanced
 };
 
 constexpr int kMaxSnapLds = 1024;

@@ -345,6 +345,7 @@ struct Lane {
     R v1[3], v2[3];     // packed layout: the current cell's face velocities (low, high face)
     int32_t fl;         // packed layout: the current cell's flag word
     int32_t nc0;        // pathline: crossings before this call
+    int32_t zrun;       // quadtree: zero-time crossings in a row
     int64_t pq, pend;   // pathline record pass: next slot, end of the particle's slots
 };
 
@@ -353,6 +354,9 @@ __device__ __forceinline__ const GridDev& grid_of(const TrackParams& P, int32_t 
     if constexpr (BATCHED) return P.grids[g];
     else return P.g0;
 }
+
+// Layouts whose cells are packed records (structured records, quadtree records).
+template <int LAYOUT> constexpr bool kPacked = (LAYOUT == L_CELL || LAYOUT == L_QUAD);
 
 // Gather one packed cell record: face velocities (with the direction sign) and the flag word.
 template <int PREC>
@@ -383,7 +387,7 @@ template <int PREC, int LAYOUT>
 __device__ __forceinline__ void load_cell(const GridDev& G, const Lane<PREC>& L, double sign,
                                           typename Real<PREC>::T (&u1)[3],
                                           typename Real<PREC>::T (&u2)[3], int32_t& fl) {
-    if constexpr (LAYOUT == L_CELL) {
+    if constexpr (kPacked<LAYOUT>) {
         if constexpr (PREC == P64) {
             const double2* r = reinterpret_cast<const double2*>(G.rec64 + L.c);
             const double2 a = r[0], b = r[1], d = r[2];
@@ -434,9 +438,25 @@ __device__ __forceinline__ void global_xyz(const GridDev& G, int32_t i, int32_t 
     out[2] = G.z0 + ((double)k + d) * G.dz;
 }
 
+// Global position of local coordinates (a, b, d) in cell c: from (i, j, k) on a structured
+// grid, from the cell's box on a quadtree grid.
+template <int LAYOUT>
+__device__ __forceinline__ void cell_xyz(const GridDev& G, int32_t c, int32_t i, int32_t j, int32_t k, double a,
+                                         double b, double d, double* out) {
+    if constexpr (LAYOUT == L_QUAD) {
+        const QuadBox& B = G.qbox[c];
+        out[0] = B.lo[0] + a * B.h[0];
+        out[1] = B.lo[1] + b * B.h[1];
+        out[2] = B.lo[2] + d * B.h[2];
+    } else {
+        (void)c;
+        global_xyz(G, i, j, k, a, b, d, out);
+    }
+}
+
 // Positions at the snapshot times s with s < to (or s <= to when closed), evaluated from the
 // state at the start of the step with tau = s - t.
-template <int PREC>
+template <int PREC, int LAYOUT>
 __device__ __forceinline__ void write_snaps(Lane<PREC>& L, const GridDev& G,
                                             const typename Real<PREC>::T (&u1)[3],
                                             const typename Real<PREC>::T (&u2)[3],
@@ -450,7 +470,7 @@ __device__ __forceinline__ void write_snaps(Lane<PREC>& L, const GridDev& G,
         const double a = (double)adv<PREC>(u1[0], u2[0], L.x[0], tau, L.amb);
         const double b = (double)adv<PREC>(u1[1], u2[1], L.x[1], tau, L.amb);
         const double d = (double)adv<PREC>(u1[2], u2[2], L.x[2], tau, L.amb);
-        global_xyz(G, L.i, L.j, L.k, a, b, d, row + 3 * (int64_t)L.ks);
+        cell_xyz<LAYOUT>(G, L.c, L.i, L.j, L.k, a, b, d, row + 3 * (int64_t)L.ks);
         ++L.ks;
         L.s_next = (L.ks < P.n_snap) ? snap[L.ks] : dinf();
     }
@@ -511,7 +531,7 @@ __device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap
                 const int32_t plane = G.nx * G.ny;
                 const int32_t k = c / plane, rem = c - k * plane;
                 const int32_t j = rem / G.nx, i = rem - j * G.nx;
-                global_xyz(G, i, j, k, P.xi[p], P.eta[p], P.zeta[p], o);
+                cell_xyz<LAYOUT>(G, c, i, j, k, P.xi[p], P.eta[p], P.zeta[p], o);
             }
         }
         return ST_SKIP;
@@ -521,7 +541,7 @@ __device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap
     bool bad = (c < 0 || (int64_t)c >= ncell);
     int32_t own = 0;
     if (!bad) {
-        if constexpr (LAYOUT == L_CELL) {
+        if constexpr (kPacked<LAYOUT>) {
             own = (PREC == P64) ? G.rec64[c].flags : G.rec32[c].flags;
         } else {
             own = G.flags[c];
@@ -537,8 +557,9 @@ __device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap
         }
         return ST_INVALID;
     }
-    if constexpr (LAYOUT == L_CELL) load_rec<PREC>(G, c, P.sign, L.v1, L.v2, L.fl);
+    if constexpr (kPacked<LAYOUT>) load_rec<PREC>(G, c, P.sign, L.v1, L.v2, L.fl);
     L.c = c;
+    L.zrun = 0;
     const int32_t plane = G.nx * G.ny;
     L.k = c / plane;
     const int32_t rem = c - L.k * plane;
@@ -577,7 +598,7 @@ __device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap
 }
 
 // Write the final state of a tracked particle.
-template <int PREC, int OUT, bool BATCHED>
+template <int PREC, int LAYOUT, int OUT, bool BATCHED>
 __device__ void finish(Lane<PREC>& L, int32_t st, const TrackParams& P, unsigned int* s_hist) {
     const int64_t p = L.pid;
     atomicAdd(&s_hist[st], 1u);
@@ -601,9 +622,77 @@ __device__ void finish(Lane<PREC>& L, int32_t st, const TrackParams& P, unsigned
     P.hash[p] = L.hash;
     if (P.out_xyz) {
         const GridDev& G = grid_of<BATCHED>(P, L.g);
-        global_xyz(G, L.i, L.j, L.k, (double)L.x[0], (double)L.x[1], (double)L.x[2], P.out_xyz + 3 * p);
+        cell_xyz<LAYOUT>(G, L.c, L.i, L.j, L.k, (double)L.x[0], (double)L.x[1], (double)L.x[2], P.out_xyz + 3 * p);
     }
     if constexpr (OUT == O_SERIES) nan_rest(L, P);
+}
+
+// Quadtree transfer (after the crossing through face f of axis `axis`): the subface holding
+// the exit point (the first in order on an edge between two) gives the neighbour; in it, a
+// face coordinate carries over when both cells span the same range on that axis and is
+// mapped through the global coordinate otherwise.  A particle handed round a point in
+// kQuadZeroRun zero-time crossings in a row (face velocities of split faces are averages,
+// so they can circulate there) stops as stranded.
+constexpr int kQuadZeroRun = 16;
+
+template <int PREC, int OUT>
+__device__ int32_t quad_transfer(Lane<PREC>& L, const GridDev& G, const TrackParams& P, const double* snap,
+                                 int32_t axis, int32_t f, double xe, double dt) {
+    const QuadRec& R = reinterpret_cast<const QuadRec*>(G.rec64)[L.c];
+    const uint32_t counts = R.counts;
+    int32_t q0 = R.sub_base;
+    for (int32_t g = 0; g < f; ++g) q0 += (int32_t)((counts >> (5 * g)) & 31u);
+    const int32_t q1 = q0 + (int32_t)((counts >> (5 * f)) & 31u);
+    const int ta1 = (axis == 0) ? 1 : 0;
+    const int ta2 = (axis == 2) ? 1 : 2;
+    const double t1 = (ta1 == 0) ? (double)L.x[0] : (double)L.x[1];
+    const double t2 = (ta2 == 1) ? (double)L.x[1] : (double)L.x[2];
+    int32_t hit = q1 - 1;
+    for (int32_t q = q0; q < q1; ++q) {
+        const double4 r = G.sub_rect[q];
+        if (r.x <= t1 && t1 <= r.z && r.y <= t2 && t2 <= r.w) {
+            hit = q;
+            break;
+        }
+    }
+    const int32_t nb = (q1 > q0) ? G.sub_nb[hit] : -1;
+    if (nb < 0) return ST_BOUNDARY;
+    const int32_t nfl = G.rec64[nb].flags;
+    if (!(nfl & CF_ACTIVE)) return ST_INACTIVE_NB;
+    const QuadBox& B = G.qbox[L.c];
+    const QuadBox& N = G.qbox[nb];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a == axis) continue;
+        if (N.lo[a] == B.lo[a] && N.h[a] == B.h[a]) continue;   // same span: unchanged
+        const double x = B.lo[a] + (double)L.x[a] * B.h[a];
+        double l = (x - N.lo[a]) / N.h[a];
+        l = (l < 0.0) ? 0.0 : l;
+        l = (l > 1.0) ? 1.0 : l;
+        L.x[a] = l;
+    }
+    L.x[axis] = 1.0 - xe;
+    L.c = nb;
+    if ((nfl & CF_SINK) && P.stop_at_sink) return ST_SINK;
+    if ((int64_t)L.ncross >= P.max_steps) return ST_STEP_CAP;
+    if (dt == 0.0) {
+        if (++L.zrun >= kQuadZeroRun) {
+            if constexpr (OUT == O_SERIES) {
+                // stranded on the circuit: the position holds up to t_max
+                double* row = P.snap_xyz + L.pid * (int64_t)P.n_snap * 3;
+                while (L.ks < P.n_snap && snap[L.ks] <= P.t_max) {
+                    cell_xyz<L_QUAD>(G, L.c, 0, 0, 0, (double)L.x[0], (double)L.x[1], (double)L.x[2],
+                                     row + 3 * (int64_t)L.ks);
+                    ++L.ks;
+                }
+            }
+            return ST_STRANDED;
+        }
+    } else {
+        L.zrun = 0;
+    }
+    load_rec<PREC>(G, L.c, P.sign, L.v1, L.v2, L.fl);
+    return 0;
 }
 
 // One cell crossing (S1-S7).  Returns 0 to continue, or the final status.
@@ -614,7 +703,7 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
     const GridDev& G = grid_of<BATCHED>(P, L.g);
     R u1[3], u2[3];
     int32_t fl;
-    if constexpr (LAYOUT == L_CELL) {
+    if constexpr (kPacked<LAYOUT>) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             u1[a] = L.v1[a];
@@ -658,13 +747,13 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
         }
     }
     if (axis < 0 && __builtin_isinf(lim)) {
-        if constexpr (OUT == O_SERIES) write_snaps<PREC>(L, G, u1, u2, P, snap, dinf(), true);
+        if constexpr (OUT == O_SERIES) write_snaps<PREC, LAYOUT>(L, G, u1, u2, P, snap, dinf(), true);
         return ST_STRANDED;
     }
     const double t_exit = L.t + dt;
     if (t_exit > lim) {
         const double tau = lim - L.t;
-        if constexpr (OUT == O_SERIES) write_snaps<PREC>(L, G, u1, u2, P, snap, lim, true);
+        if constexpr (OUT == O_SERIES) write_snaps<PREC, LAYOUT>(L, G, u1, u2, P, snap, lim, true);
 #pragma unroll
         for (int a = 0; a < 3; ++a) L.x[a] = adv<PREC>(u1[a], u2[a], L.x[a], tau, L.amb);
         L.t = lim;
@@ -674,7 +763,7 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
                 L.g += 1;
                 const GridDev& G2 = grid_of<BATCHED>(P, L.g);
                 int32_t own;
-                if constexpr (LAYOUT == L_CELL) {
+                if constexpr (kPacked<LAYOUT>) {
                     load_rec<PREC>(G2, L.c, P.sign, L.v1, L.v2, L.fl);
                     own = L.fl;
                 } else {
@@ -693,7 +782,7 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
     const int32_t step = hi ? 1 : -1;
 
     // advance to the exit face: the two other axes move analytically
-    if constexpr (OUT == O_SERIES) write_snaps<PREC>(L, G, u1, u2, P, snap, t_exit, false);
+    if constexpr (OUT == O_SERIES) write_snaps<PREC, LAYOUT>(L, G, u1, u2, P, snap, t_exit, false);
     {
         const int a1 = (axis == 0) ? 1 : 0;
         const int a2 = (axis == 2) ? 1 : 2;
@@ -720,7 +809,7 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
             if (q >= 0 && q < L.pend) {
                 // one 40-byte record: a particle's records form one contiguous stream
                 double xyz[3];
-                global_xyz(G, L.i, L.j, L.k, (double)L.x[0], (double)L.x[1], (double)L.x[2], xyz);
+                cell_xyz<LAYOUT>(G, L.c, L.i, L.j, L.k, (double)L.x[0], (double)L.x[1], (double)L.x[2], xyz);
                 PathRec r;
                 r.t = L.t;
                 r.x = xyz[0];
@@ -734,6 +823,8 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
             }
         }
     }
+
+    if constexpr (LAYOUT == L_QUAD) return quad_transfer<PREC, OUT>(L, G, P, snap, axis, f, xe, dt);
 
     // transfer to the neighbour across the exit face
     int32_t nfl_sink;
@@ -766,7 +857,7 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
     if (nfl_sink && P.stop_at_sink) return ST_SINK;
     if ((int64_t)L.ncross >= P.max_steps) return ST_STEP_CAP;
     // the particle continues: gather the new cell's record
-    if constexpr (LAYOUT == L_CELL) load_rec<PREC>(G, L.c, P.sign, L.v1, L.v2, L.fl);
+    if constexpr (kPacked<LAYOUT>) load_rec<PREC>(G, L.c, P.sign, L.v1, L.v2, L.fl);
     return 0;
 }
 
@@ -838,7 +929,7 @@ __global__ void __launch_bounds__(kBlock) k_track_static(TrackParams P) {
         L.pid = P.order ? (int64_t)P.order[slot] : slot;
         int32_t st = begin<PREC, LAYOUT, OUT, BATCHED>(L, P, snap);
         while (st == 0) st = track_step<PREC, LAYOUT, OUT, BATCHED>(L, P, snap, crossings);
-        if (st > 0) finish<PREC, OUT, BATCHED>(L, st, P, S.hist);
+        if (st > 0) finish<PREC, LAYOUT, OUT, BATCHED>(L, st, P, S.hist);
     }
     block_flush(S, P, crossings, L.amb, L.drop);
 }
@@ -898,7 +989,7 @@ __global__ void __launch_bounds__(kBlock) k_track_persistent(TrackParams P) {
                     L.pid = P.order ? (int64_t)P.order[slot] : slot;
                     const int32_t st = begin<PREC, LAYOUT, OUT, BATCHED>(L, P, snap);
                     if (st != 0) {
-                        if (st > 0) finish<PREC, OUT, BATCHED>(L, st, P, S.hist);
+                        if (st > 0) finish<PREC, LAYOUT, OUT, BATCHED>(L, st, P, S.hist);
                         L.pid = -1;
                     }
                 }
@@ -919,7 +1010,7 @@ __global__ void __launch_bounds__(kBlock) k_track_persistent(TrackParams P) {
             if (L.pid >= 0) {
                 const int32_t st = track_step<PREC, LAYOUT, OUT, BATCHED>(L, P, snap, crossings);
                 if (st != 0) {
-                    finish<PREC, OUT, BATCHED>(L, st, P, S.hist);
+                    finish<PREC, LAYOUT, OUT, BATCHED>(L, st, P, S.hist);
                     L.pid = -1;
                 }
             }
@@ -1062,6 +1153,47 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_add(ScanParams S) {
         if (base + q < S.n) S.v[base + q] += add;
 }
 
+// Quadtree grid load: each face's total flow (its subfaces summed in order), the velocities
+// u = Q / (n V), the own flags, the first subface and the per-face subface counts.
+__global__ void __launch_bounds__(256) k_build_quad(BuildQuadParams B) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= B.ncell) return;
+    const QuadBox& X = B.box[c];
+    const double V = (X.h[0] * X.h[1]) * X.h[2];
+    const double n_c = B.por ? B.por[c] : B.por_scalar;
+    const int32_t own = B.flags ? B.flags[c] : CF_ACTIVE;
+    double Q[6];
+    bool finite = true;
+    uint32_t counts = 0u;
+    for (int f = 0; f < 6; ++f) {
+        const int32_t a = B.sub_off[6 * c + f], b = B.sub_off[6 * c + f + 1];
+        double q = 0.0;
+        for (int32_t s = a; s < b; ++s) {
+            finite = finite && __builtin_isfinite(B.sub_q[s]);
+            q += B.sub_q[s];
+        }
+        Q[f] = q;
+        counts |= (uint32_t)(b - a) << (5 * f);
+    }
+    if (!finite) atomicOr(&B.err[0], 1);
+    if (!(n_c > 0.0) || !__builtin_isfinite(n_c)) atomicOr(&B.err[1], 1);
+    if (own & ~(CF_ACTIVE | CF_SINK)) atomicOr(&B.err[2], 1);
+    if (B.balance_tol >= 0.0 && (own & CF_ACTIVE) && !(own & CF_SINK) && finite) {
+        const double net = (Q[0] - Q[1]) + (Q[2] - Q[3]) + (Q[4] - Q[5]);
+        double gross = 0.0;
+        for (int32_t s = B.sub_off[6 * c]; s < B.sub_off[6 * c + 6]; ++s) gross += fabs(B.sub_q[s]);
+        if (fabs(net) > B.balance_tol * gross) atomicOr(&B.err[3], 1);
+    }
+    const double d = n_c * V;
+    QuadRec r;
+    for (int f = 0; f < 6; ++f) r.u[f] = Q[f] / d;
+    r.flags = own & (CF_ACTIVE | CF_SINK);
+    r.sub_base = B.sub_off[6 * c];
+    r.counts = counts;
+    r.pad0 = 0;
+    B.rec[c] = r;
+}
+
 // Grid load: validate the field and build both packed records of every cell.
 __global__ void __launch_bounds__(256) k_build(BuildParams B) {
     const GridDev& G = B.g;
@@ -1142,6 +1274,11 @@ const void* pick_out(const KernelKey& k) {
 }  // namespace
 
 const void* track_kernel(const KernelKey& k) {
+    if (k.layout == L_QUAD) {   // FP64, single grid
+        if (k.out == O_SERIES) return pick_sched<P64, L_QUAD, O_SERIES, false>(k.sched);
+        if (k.out == O_PATH) return pick_sched<P64, L_QUAD, O_PATH, false>(k.sched);
+        return pick_sched<P64, L_QUAD, O_END, false>(k.sched);
+    }
     if (k.precision == PMIX) return pick_out<PMIX, L_CELL>(k);
     if (k.layout == L_FACES) return pick_out<P64, L_FACES>(k);
     return pick_out<P64, L_CELL>(k);
@@ -1156,5 +1293,6 @@ const void* scan_tiles_kernel() { return reinterpret_cast<const void*>(&k_scan_t
 const void* scan_partials_kernel() { return reinterpret_cast<const void*>(&k_scan_partials); }
 const void* scan_add_kernel() { return reinterpret_cast<const void*>(&k_scan_add); }
 const void* build_kernel() { return reinterpret_cast<const void*>(&k_build); }
+const void* build_quad_kernel() { return reinterpret_cast<const void*>(&k_build_quad); }
 
 }  // namespace pt

@@ -43,6 +43,13 @@ class pt_grid_desc(ctypes.Structure):
                 ("balance_tol", ctypes.c_double)]
 
 
+class pt_quad_desc(ctypes.Structure):
+    _fields_ = [("ncell", ctypes.c_int32), ("nsub", ctypes.c_int32), ("box", _p), ("sub_off", _p),
+                ("sub_nb", _p), ("sub_q", _p), ("sub_lo", _p), ("sub_hi", _p), ("porosity", _p),
+                ("porosity_scalar", ctypes.c_double), ("flags", _p), ("mem", ctypes.c_int32),
+                ("balance_tol", ctypes.c_double)]
+
+
 class pt_particles(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("cell", _p), ("xi", _p), ("eta", _p), ("zeta", _p), ("t", _p),
                 ("status", _p), ("ncross", _p), ("path_hash", _p), ("n_groups", ctypes.c_int32),
@@ -80,7 +87,7 @@ class pt_summary(ctypes.Structure):
                 ("path_records", ctypes.c_int64), ("path_dropped", ctypes.c_int64)]
 
 
-EXPORTS = ["pt_load_grid", "pt_track", "pt_results", "pt_release", "pt_last_error", "pt_default_opts",
+EXPORTS = ["pt_load_grid", "pt_load_quad_grid", "pt_track", "pt_results", "pt_release", "pt_last_error", "pt_default_opts",
            "pt_version"]
 
 _lib = None
@@ -96,6 +103,8 @@ def load_library(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     lib.pt_load_grid.argtypes = [ctypes.POINTER(pt_grid_desc), _p, ctypes.POINTER(_p)]
     lib.pt_load_grid.restype = ctypes.c_int
+    lib.pt_load_quad_grid.argtypes = [ctypes.POINTER(pt_quad_desc), _p, ctypes.POINTER(_p)]
+    lib.pt_load_quad_grid.restype = ctypes.c_int
     lib.pt_track.argtypes = [ctypes.POINTER(_p), ctypes.c_int32, ctypes.POINTER(pt_particles),
                              ctypes.POINTER(pt_track_opts), _p, ctypes.POINTER(_p)]
     lib.pt_track.restype = ctypes.c_int
@@ -186,6 +195,35 @@ def pt_load_grid(grid, stream=None, balance_tol: float = -1.0) -> Grid:
     out = _p()
     _check(lib.pt_load_grid(ctypes.byref(d), _stream_ptr(stream), ctypes.byref(out)))
     return Grid(out.value, grid.nx, grid.ny, grid.nz)
+
+
+def pt_load_quad_grid(q, stream=None, balance_tol: float = -1.0) -> Grid:
+    """Load a quadtree grid (an object with ncell, box, sub_off, sub_nb, sub_q, sub_lo, sub_hi,
+    flags, porosity, porosity_scalar as numpy arrays, e.g. workloads.quadtree.QuadGrid)."""
+    lib = load_library()
+    keep = []
+
+    def conv(a, dtype):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dtype)
+        keep.append(a)
+        return a.ctypes.data
+
+    d = pt_quad_desc(q.ncell, int(q.sub_nb.shape[0]), conv(q.box, np.float64), conv(q.sub_off, np.int32),
+                     conv(q.sub_nb, np.int32), conv(q.sub_q, np.float64), conv(q.sub_lo, np.float64),
+                     conv(q.sub_hi, np.float64), conv(q.porosity, np.float64), q.porosity_scalar,
+                     conv(q.flags, np.int32), PT_MEM_HOST, balance_tol)
+    out = _p()
+    _check(lib.pt_load_quad_grid(ctypes.byref(d), _stream_ptr(stream), ctypes.byref(out)))
+    return Grid(out.value, q.ncell, 1, 1)
+
+
+def load_any_grid(g, stream=None, balance_tol: float = -1.0) -> Grid:
+    """pt_load_quad_grid for quadtree grids (objects with sub_off), pt_load_grid otherwise."""
+    if hasattr(g, "sub_off"):
+        return pt_load_quad_grid(g, stream, balance_tol)
+    return pt_load_grid(g, stream, balance_tol)
 
 
 def pt_release(handle) -> None:

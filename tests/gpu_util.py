@@ -22,7 +22,7 @@ def gpu_track(grids_np, particles, *, group_offsets=None, group_grid=None, snap_
     """Load the grids, copy the particles to the device, track, return numpy outputs + summary."""
     from paper_2302_13590_amd import pt
     dev = "cuda"
-    handles = [pt.pt_load_grid(g) for g in grids_np]
+    handles = [pt.load_any_grid(g) for g in grids_np]
     try:
         dp = pt.DeviceParticles.from_numpy(particles, dev)
         n = dp.n

@@ -14,6 +14,11 @@ int main(void) {
     F(pt_grid_desc, z0); F(pt_grid_desc, qx); F(pt_grid_desc, qy); F(pt_grid_desc, qz);
     F(pt_grid_desc, porosity); F(pt_grid_desc, porosity_scalar); F(pt_grid_desc, flags);
     F(pt_grid_desc, mem); F(pt_grid_desc, balance_tol);
+    S(pt_quad_desc);
+    F(pt_quad_desc, ncell); F(pt_quad_desc, nsub); F(pt_quad_desc, box); F(pt_quad_desc, sub_off);
+    F(pt_quad_desc, sub_nb); F(pt_quad_desc, sub_q); F(pt_quad_desc, sub_lo); F(pt_quad_desc, sub_hi);
+    F(pt_quad_desc, porosity); F(pt_quad_desc, porosity_scalar); F(pt_quad_desc, flags);
+    F(pt_quad_desc, mem); F(pt_quad_desc, balance_tol);
     S(pt_particles);
     F(pt_particles, n); F(pt_particles, cell); F(pt_particles, xi); F(pt_particles, eta);
     F(pt_particles, zeta); F(pt_particles, t); F(pt_particles, status); F(pt_particles, ncross);

@@ -56,7 +56,8 @@ def test_struct_layouts_match_binding():
         if ln:
             k, v = ln.split()
             c[k] = int(v)
-    for T in (pt.pt_grid_desc, pt.pt_particles, pt.pt_track_opts, pt.pt_summary, pt.pt_path_record):
+    for T in (pt.pt_grid_desc, pt.pt_quad_desc, pt.pt_particles, pt.pt_track_opts, pt.pt_summary,
+              pt.pt_path_record):
         assert ctypes.sizeof(T) == c[T.__name__ + ".sizeof"], T.__name__
         for name, _ in T._fields_:
             assert getattr(T, name).offset == c["%s.%s" % (T.__name__, name)], (T.__name__, name)
@@ -123,6 +124,51 @@ def test_load_grid_data_validation(lib):
     if not _gpu():
         d, keep = _desc(g, balance_tol=1e-12)        # valid and balanced: needs a device
         assert _load(lib, d)[0] == -4
+
+
+def test_quad_grid_validation(lib):
+    """pt_load_quad_grid checks the description on the host before any device work."""
+    from workloads import quadtree as QT
+    g = C.random_grid(8, 8, 2, 1.0, 2.0, 5)
+    q = QT.from_structured(g, QT.block_sizes(8, 8, [(2, 2)], r1=1.0, r2=3.0))
+    keep = {}
+
+    def desc(**kw):
+        arrs = dict(box=q.box, sub_off=q.sub_off, sub_nb=q.sub_nb, sub_q=q.sub_q, sub_lo=q.sub_lo,
+                    sub_hi=q.sub_hi, flags=q.flags)
+        arrs.update({k: v for k, v in kw.items() if k in arrs})
+        dt = dict(sub_off=np.int32, sub_nb=np.int32, flags=np.int32)
+        for k, v in arrs.items():
+            keep[k] = np.ascontiguousarray(v, dtype=dt.get(k, np.float64))
+        d = pt.pt_quad_desc(kw.get("ncell", q.ncell), kw.get("nsub", q.nsub), *(keep[k].ctypes.data for k in
+                            ("box", "sub_off", "sub_nb", "sub_q", "sub_lo", "sub_hi")), None,
+                            kw.get("porosity_scalar", 0.3), keep["flags"].ctypes.data, kw.get("mem", pt.PT_MEM_HOST),
+                            -1.0)
+        return d
+
+    def load(d):
+        out = ctypes.c_void_p()
+        return lib.pt_load_quad_grid(ctypes.byref(d), None, ctypes.byref(out))
+
+    assert lib.pt_load_quad_grid(None, None, None) == -1
+    off_bad = q.sub_off.copy()
+    off_bad[3] = off_bad[5] + 1                      # decreasing
+    nb_bad = q.sub_nb.copy()
+    nb_bad[3] = q.ncell
+    lo_bad = q.sub_lo.copy()
+    lo_bad[0, 0] = 1.5                               # outside [0, 1]
+    box_bad = q.box.copy()
+    box_bad[1, 3] = 0.0
+    for name, d in (("ncell", desc(ncell=0)), ("nsub", desc(nsub=-1)), ("sub_off", desc(sub_off=off_bad)),
+                    ("sub_nb", desc(sub_nb=nb_bad)), ("sub_lo", desc(sub_lo=lo_bad)), ("box", desc(box=box_bad)),
+                    ("porosity", desc(porosity_scalar=0.0))):
+        assert load(d) == -1, name
+    assert load(desc(mem=pt.PT_MEM_DEVICE)) == -7
+    many = q.sub_off.copy()
+    many[1:] += 40                                   # face 0 of cell 0 would hold 40 subfaces
+    assert load(desc(sub_off=many, nsub=q.nsub + 40)) in (-1, -7)
+    rc = load(desc())
+    assert rc in (0, -4, -5), rc                     # valid: no device here, or loaded
 
 
 def test_track_validation_without_grid(lib):

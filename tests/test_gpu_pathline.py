@@ -44,7 +44,7 @@ def oracle_paths(grid, p, **kw):
 
 
 def gpu_pathlines(pt, grids, p, group_offsets=None, group_grid=None, **opt):
-    handles = [pt.pt_load_grid(g) for g in grids]
+    handles = [pt.load_any_grid(g) for g in grids]
     try:
         dp = pt.DeviceParticles.from_numpy(p, "cuda")
         oxyz = torch.full((dp.n, 3), float("nan"), dtype=torch.float64, device="cuda")
