@@ -5,7 +5,10 @@ One step = one pass of the whole tracking path over one batch: restore the
 released particle state (device-to-device copy), track every particle to its
 stopping condition through the C ABI (pt_track: counter reset + tracking
 kernel), and read the run summary (pt_results).  Grids and particles are
-resident in HBM before the timed region starts.
+resident in HBM before the timed region starts.  The K timed steps are
+enqueued back to back on one stream and their summaries read afterwards, so
+the timed region holds the device work of K steps and no host wait between
+them.
 
 Default workload (C2): 100x100x10 cells of 10x10x2 m, lognormal K with
 geometric mean 10 m/d, sigma^2 = 1, correlation length 5 cells, heads 10/0 m
@@ -57,20 +60,11 @@ def host_cpu_model():
 
 
 def workload(name):
-    from workloads import configs as C
-    if name == "C1":
-        return C.c1()
-    if name == "C2":
-        return C.c2()
-    if name == "C3":
-        return C.c3()
-    if name == "C4":
-        return C.c4()
-    if name == "C5":
-        return C.c5()
-    if name == "C6":
-        return C.c6()
-    raise SystemExit("unknown workload " + name)
+    import workloads
+    try:
+        return workloads.workload(name)
+    except KeyError:
+        raise SystemExit("unknown workload " + name)
 
 
 DESCR = {
@@ -81,6 +75,8 @@ DESCR = {
     "C5": "C5: 200x200x20 lognormal K (sigma^2=2), 1e6 particles, timeseries 100 snapshots [1e6,100,3]",
     "C6": "C6: C2's grid under transient flow (12 time steps, a well switching on and off), 1e6 particles "
           "released in 10 stages, weak sinks pass through",
+    "C7": "C7: quadtree grid, 3-layer aquifer refined around two wells (16,455 cells from 256x256x3 fine), "
+          "1e6 particles over the top layer",
 }
 
 
@@ -91,7 +87,7 @@ class Case:
         import torch
         from paper_2302_13590_amd import pt
         self.pt, self.torch, self.w = pt, torch, w
-        self.grids = [pt.pt_load_grid(g) for g in w.grids]
+        self.grids = [pt.load_any_grid(g) for g in w.grids]
         self.pristine = pt.DeviceParticles.from_numpy(w.particles, "cuda")
         self.work = self.pristine.clone()
         n = self.pristine.n
@@ -123,13 +119,29 @@ class Case:
         run.release()
         return s
 
+    def enqueue(self, o):
+        """Restore the state and enqueue one tracking call (no host wait)."""
+        self.work.copy_(self.pristine)
+        return self.pt.pt_track(self.grids, self.work, o, stream=self.stream,
+                                group_offsets=self.w.group_offsets, group_grid=self.w.group_grid)
+
+    def run_steps(self, o, steps):
+        """`steps` steps enqueued back to back on the stream, then their summaries."""
+        runs = [self.enqueue(o) for _ in range(steps)]
+        summ = [self.pt.pt_results(r) for r in runs]
+        for r in runs:
+            r.release()
+        return summ
+
     def time(self, o, steps, warmup):
         torch = self.torch
-        for _ in range(warmup):
-            self.step(o)
+        if warmup > 0:
+            for _ in range(warmup):
+                self.step(o)
+            self.run_steps(o, steps)       # every pooled run has built its graph
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        summ = [self.step(o) for _ in range(steps)]
+        summ = self.run_steps(o, steps)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         cross = summ[0]["crossings"]
@@ -152,23 +164,30 @@ class Case:
         orec = self.opts(precision, schedule_name, mode=pt.PT_PATHLINE, path_offsets=offs, path_count_only=0,
                          path_cap=m, path_records=records, **kw)
 
-        def one():
+        def enqueue():
             self.work.copy_(self.pristine)
             a = pt.pt_track(self.grids, self.work, oc, stream=self.stream,
                             group_offsets=self.w.group_offsets, group_grid=self.w.group_grid)
             b = pt.pt_track(self.grids, self.work, orec, stream=self.stream,
                             group_offsets=self.w.group_offsets, group_grid=self.w.group_grid)
-            sa, sb = pt.pt_results(a), pt.pt_results(b)
-            a.release()
-            b.release()
-            assert sa["path_records"] == m and sb["path_records"] == m and sb["path_dropped"] == 0
-            return sa, sb
+            return a, b
 
-        for _ in range(warmup):
-            one()
+        def run_steps(k):
+            runs = [enqueue() for _ in range(k)]
+            out = []
+            for a, b in runs:
+                sa, sb = pt.pt_results(a), pt.pt_results(b)
+                a.release()
+                b.release()
+                assert sa["path_records"] == m and sb["path_records"] == m and sb["path_dropped"] == 0
+                out.append((sa, sb))
+            return out
+
+        if warmup > 0:
+            run_steps(max(warmup, steps))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        summ = [one() for _ in range(steps)]
+        summ = run_steps(steps)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         cross = summ[0][1]["crossings"]
@@ -323,8 +342,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the tracker on a single MI355X "
-              "(particles are independent; see DESIGN.md for how the path would shard).", file=sys.stderr)
+        print("bench.py measures one GPU: the tracker runs on a single MI355X (particles are independent, "
+              "so the path would shard by particle with no exchange until a final reduction of the counters).",
+              file=sys.stderr)
         return 2
     import torch
     if not torch.cuda.is_available():
@@ -353,9 +373,9 @@ def main():
     log("inputs ready in %.1fs: %d particles, %d grid(s)" % (time.perf_counter() - t0, n, len(w.grids)))
     case = Case(w)
 
-    def launch(precision, schedule):
+    def launch(precision, schedule, wname=args.workload, wmode=mode):
         """Launch parameters: the autotuned ones when they use this schedule, else defaults."""
-        tuned = tuned_params(args.workload, precision, mode) or {}
+        tuned = tuned_params(wname, precision, wmode) or {}
         sched_id = 1 if schedule == "static" else 2
         if schedule == "auto" and tuned:
             return tuned, ("static" if tuned.get("schedule") == 1 else "persistent")
@@ -392,6 +412,19 @@ def main():
             log("variant pathline: %.4g crossings/s, count %.3f ms + record %.3f ms" % (
                 r["value"], r["count_ms"], r["record_ms"]))
     case.release()
+    if not args.only and args.workload == "C2":
+        # the transient-flow and quadtree workloads, FP64, their tuned launches
+        for wname, tag in (("C6", "fp64_transient_C6"), ("C7", "fp64_quadtree_C7")):
+            t0 = time.perf_counter()
+            c2 = Case(workload(wname))
+            log("%s ready in %.1fs" % (wname, time.perf_counter() - t0))
+            p2, s2 = launch("fp64", "auto", wname, "endpoint")
+            r = c2.time(c2.opts("fp64", s2, **p2), args.steps, args.warmup)
+            c2.release()
+            variants[tag] = dict(value=r["value"], ms_per_step=round(r["ms_per_step"], 4),
+                                 kernel_ms=round(r["kernel_ms"], 4), crossings_per_step=r["crossings_per_step"],
+                                 launch=p2, workload=DESCR[wname])
+            log("variant %s: %.4g crossings/s, kernel %.3f ms" % (tag, r["value"], r["kernel_ms"]))
 
     out = {
         "metric": METRIC,

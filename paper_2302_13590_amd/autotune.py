@@ -100,16 +100,19 @@ def main(argv=None):
         sys.path.insert(0, root)
     import torch
     from paper_2302_13590_amd import pt
-    from workloads import configs as C
+    import workloads
 
-    w = C.CONFIGS[args.workload]()
-    grids = [pt.pt_load_grid(g) for g in w.grids]
+    w = workloads.workload(args.workload)
+    grids = [pt.load_any_grid(g) for g in w.grids]
     pristine = pt.DeviceParticles.from_numpy(w.particles, "cuda")
     work = pristine.clone()
     n = pristine.n
     out_xyz = torch.empty((n, 3), dtype=torch.float64, device="cuda")
     base = dict(precision=pt.PT_MIXED if args.precision == "mixed" else pt.PT_FP64,
-                layout=pt.PT_LAYOUT_CELL, use_graph=1, out_xyz=out_xyz, t_max=w.t_max)
+                layout=pt.PT_LAYOUT_CELL, use_graph=1, out_xyz=out_xyz, t_max=w.t_max,
+                stop_at_sink=w.stop_at_sink)
+    if w.tstep_end is not None:
+        base.update(tstep_end=w.tstep_end)
     mode = "endpoint"
     if w.snap_times is not None:
         snap = torch.empty((n, len(w.snap_times), 3), dtype=torch.float64, device="cuda")

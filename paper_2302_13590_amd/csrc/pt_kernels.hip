@@ -671,7 +671,10 @@ __device__ int32_t quad_transfer(Lane<PREC>& L, const GridDev& G, const TrackPar
         l = (l > 1.0) ? 1.0 : l;
         L.x[a] = l;
     }
-    L.x[axis] = 1.0 - xe;
+    // constant indices only: the lane state stays in registers
+    L.x[0] = (axis == 0) ? 1.0 - xe : L.x[0];
+    L.x[1] = (axis == 1) ? 1.0 - xe : L.x[1];
+    L.x[2] = (axis == 2) ? 1.0 - xe : L.x[2];
     L.c = nb;
     if ((nfl & CF_SINK) && P.stop_at_sink) return ST_SINK;
     if ((int64_t)L.ncross >= P.max_steps) return ST_STEP_CAP;

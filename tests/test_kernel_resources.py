@@ -1,0 +1,54 @@
+"""Build properties of the tracking kernels (compiled for gfx950 on the CPU, not run): no
+kernel spills its lane state to scratch memory (dynamic indexing of the per-lane arrays or
+register spills would put every step's state in memory), and every tracking kernel keeps at
+least two waves per SIMD."""
+import os
+import re
+import shutil
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+@pytest.fixture(scope="module")
+def usage():
+    sys.path.insert(0, ROOT)
+    from paper_2302_13590_amd import build as B
+    if not os.path.exists(B.HIPCC) and not shutil.which("hipcc"):
+        pytest.skip("hipcc not available")
+    src = os.path.join(B.CSRC, "pt_kernels.hip")
+    with tempfile.TemporaryDirectory() as d:
+        flags = [f for f in B.FLAGS if f not in ("-shared", "-fPIC")]
+        r = subprocess.run([B.HIPCC] + flags + ["-I", B.INCLUDE, "-c", src, "-o", os.path.join(d, "k.o"),
+                            "-Rpass-analysis=kernel-resource-usage"], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    out = {}
+    name = None
+    for line in r.stderr.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            out[name] = {}
+            continue
+        m = re.search(r"remark: \s*([A-Za-z ]+?)(?: \[[^\]]*\])?: (\d+)", line)
+        if name and m:
+            out[name][m.group(1).strip()] = int(m.group(2))
+    assert out, "no resource remarks parsed"
+    return out
+
+
+def test_no_scratch(usage):
+    spill = {k: v.get("ScratchSize", 0) for k, v in usage.items() if v.get("ScratchSize", 0) > 0}
+    assert not spill, spill
+
+
+def test_tracking_kernel_occupancy(usage):
+    occ = {k: v.get("Occupancy", 0) for k, v in usage.items() if "k_track_" in k}
+    assert len(occ) >= 30, sorted(occ)
+    low = {k: o for k, o in occ.items() if o < 2}
+    assert not low, low
