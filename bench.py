@@ -215,10 +215,10 @@ def kernel_sources_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(workload, precision, schedule):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel sources for this workload and launch; else None."""
-    path = os.path.join(ROOT, "profiles", "track_%s_%s_%s_counters.txt" % (precision, workload, schedule))
+def profile_value(kind, key, workload, precision, schedule):
+    """A figure of a committed rocprofv3 summary (profiles/track_<precision>_<workload>_<schedule>_
+    <kind>.txt), if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "track_%s_%s_%s_%s.txt" % (precision, workload, schedule, kind))
     if not os.path.exists(path):
         return None
     vals = {}
@@ -226,13 +226,18 @@ def profiled_traffic(workload, precision, schedule):
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
-                vals[k.strip()] = v.strip()
+                vals[k.strip()] = v.strip().split()[0] if v.strip() else ""
     if vals.get("kernel_sources_sha256") != kernel_sources_sha():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def profiled_traffic(workload, precision, schedule):
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE, WRITE_SIZE)."""
+    return profile_value("counters", "hbm_bytes_per_launch", workload, precision, schedule)
 
 
 def kernel_name(precision, schedule, timeseries=False, batched=False):
@@ -245,11 +250,16 @@ def kernel_name(precision, schedule, timeseries=False, batched=False):
 def roofline(res, n, precision, workload, schedule, timeseries=False, batched=False):
     bytes_launch = res["crossings_per_step"] * BYTES_PER_CROSSING[precision] + n * BYTES_PER_PARTICLE
     achieved = bytes_launch / (res["kernel_ms"] * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": profiled_traffic(workload, precision, schedule),
-            "bytes_per_launch": int(bytes_launch), "kernel_ms": round(res["kernel_ms"], 4),
-            "kernel": kernel_name(precision, schedule, timeseries, batched)}
+    out = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 5),
+           "traffic": profiled_traffic(workload, precision, schedule),
+           "bytes_per_launch": int(bytes_launch), "kernel_ms": round(res["kernel_ms"], 4),
+           "kernel": kernel_name(precision, schedule, timeseries, batched)}
+    # the vector-ALU view of the same kernel (issued VALU cycles over available), from counters
+    busy = profile_value("valu", "valu_busy", workload, precision, schedule)
+    if busy is not None:
+        out["valu_busy"] = busy
+    return out
 
 
 def tuned_params(workload, precision, mode):
