@@ -323,7 +323,8 @@ PT_CR_HD ExpRed exp_reduce(double x) {
     const double r0 = x - Kd * PT_CR_LN2_128_1;   // exact
     dd m = two_prod(Kd, PT_CR_LN2_128_2);
     m.l = fma(Kd, PT_CR_LN2_128_3, m.l);
-    const dd r = dd_add_fast({r0, 0.0}, {-m.h, -m.l});
+    const dd h = two_sum(r0, -m.h);
+    const dd r = fast_two_sum(h.h, h.l - m.l);
     return {K >> 7, K & 127, r};
 }
 

@@ -101,10 +101,9 @@ __device__ __forceinline__ double exit_time64(double u1, double u2, double xi, d
     return dt;
 }
 
-// Position along one axis after tau: xi + u_p tau expm1(A tau)/(A tau), clamped to [0,1].
-__device__ __forceinline__ double adv64(double u1, double u2, double xi, double tau, unsigned& amb) {
-    const double A = u2 - u1;
-    const double up = u1 + A * xi;
+// Position along one axis after tau: xi + u_p tau expm1(A tau)/(A tau), clamped to [0,1];
+// A = u2 - u1 and u_p = u1 + A xi as the exit selection already formed them.
+__device__ __forceinline__ double adv64_au(double A, double up, double xi, double tau, unsigned& amb) {
     if (up == 0.0) return xi;
     const double y = A * tau;
     const double psi = (y == 0.0) ? 1.0 : ptcr::expm1_cr(y, &amb) / y;
@@ -112,6 +111,12 @@ __device__ __forceinline__ double adv64(double u1, double u2, double xi, double 
     xn = (xn < 0.0) ? 0.0 : xn;
     xn = (xn > 1.0) ? 1.0 : xn;
     return xn;
+}
+
+__device__ __forceinline__ double adv64(double u1, double u2, double xi, double tau, unsigned& amb) {
+    const double A = u2 - u1;
+    const double up = u1 + A * xi;
+    return adv64_au(A, up, xi, tau, amb);
 }
 
 // Earliest exit over the three axes, FP64, with the same result as evaluating exit_time64 on
@@ -151,13 +156,16 @@ __device__ __forceinline__ float exit_estimate(double D, double up, double A, do
 
 __device__ __forceinline__ void select_exit64(const double (&u1)[3], const double (&u2)[3],
                                               const double (&xi)[3], double& dt, int32_t& axis,
-                                              double& xe, unsigned& amb) {
+                                              double& xe, unsigned& amb, double (&Ao)[3],
+                                              double (&upo)[3]) {
     double E[3];
     bool unsure = false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double A = u2[a] - u1[a];
         const double up = u1[a] + A * xi[a];
+        Ao[a] = A;
+        upo[a] = up;
         double ue, e;
         bool feasible;
         if (up > 0.0) {
@@ -358,6 +366,20 @@ __device__ __forceinline__ const GridDev& grid_of(const TrackParams& P, int32_t 
 // Layouts whose cells are packed records (structured records, quadtree records).
 template <int LAYOUT> constexpr bool kPacked = (LAYOUT == L_CELL || LAYOUT == L_QUAD);
 
+// Whether a lane keeps its cell's (i, j, k) up to date at every crossing: the face layout needs
+// them for its face indices, timeseries and pathline outputs for their positions.  Endpoint runs
+// on packed structured records only need them at the end, formed from the cell id there.
+template <int LAYOUT, int OUT> constexpr bool kTrackIJK = !(LAYOUT == L_CELL && OUT == O_END);
+
+// (i, j, k) of structured cell c.
+__device__ __forceinline__ void cell_ijk(const GridDev& G, int32_t c, int32_t& i, int32_t& j, int32_t& k) {
+    const int32_t plane = G.nx * G.ny;
+    k = c / plane;
+    const int32_t rem = c - k * plane;
+    j = rem / G.nx;
+    i = rem - j * G.nx;
+}
+
 // Gather one packed cell record: face velocities (with the direction sign) and the flag word.
 template <int PREC>
 __device__ __forceinline__ void load_rec(const GridDev& G, int32_t c, double sign,
@@ -367,9 +389,16 @@ __device__ __forceinline__ void load_rec(const GridDev& G, int32_t c, double sig
         const double2* r = reinterpret_cast<const double2*>(G.rec64 + c);
         const double2 a = r[0], b = r[1], d = r[2];
         fl = G.rec64[c].flags;
-        u1[0] = sign * a.x; u2[0] = sign * a.y;
-        u1[1] = sign * b.x; u2[1] = sign * b.y;
-        u1[2] = sign * d.x; u2[2] = sign * d.y;
+        u1[0] = a.x; u2[0] = a.y;
+        u1[1] = b.x; u2[1] = b.y;
+        u1[2] = d.x; u2[2] = d.y;
+        if (sign != 1.0) {   // backward tracking (uniform across the launch)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                u1[q] = sign * u1[q];
+                u2[q] = sign * u2[q];
+            }
+        }
     } else {
         const float4* r = reinterpret_cast<const float4*>(G.rec32 + c);
         const float4 a = r[0];
@@ -560,11 +589,7 @@ __device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap
     if constexpr (kPacked<LAYOUT>) load_rec<PREC>(G, c, P.sign, L.v1, L.v2, L.fl);
     L.c = c;
     L.zrun = 0;
-    const int32_t plane = G.nx * G.ny;
-    L.k = c / plane;
-    const int32_t rem = c - L.k * plane;
-    L.j = rem / G.nx;
-    L.i = rem - L.j * G.nx;
+    if constexpr (kTrackIJK<LAYOUT, OUT>) cell_ijk(G, c, L.i, L.j, L.k);
     L.x[0] = (R)a;
     L.x[1] = (R)b;
     L.x[2] = (R)d;
@@ -622,6 +647,7 @@ __device__ void finish(Lane<PREC>& L, int32_t st, const TrackParams& P, unsigned
     P.hash[p] = L.hash;
     if (P.out_xyz) {
         const GridDev& G = grid_of<BATCHED>(P, L.g);
+        if constexpr (!kTrackIJK<LAYOUT, OUT>) cell_ijk(G, L.c, L.i, L.j, L.k);
         cell_xyz<LAYOUT>(G, L.c, L.i, L.j, L.k, (double)L.x[0], (double)L.x[1], (double)L.x[2], P.out_xyz + 3 * p);
     }
     if constexpr (OUT == O_SERIES) nan_rest(L, P);
@@ -721,8 +747,9 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
     double dt = dinf();
     int32_t axis = -1;
     R xe = 0;
+    double Aa[3], upa[3];   // FP64: gradient and particle velocity of each axis at the step start
     if constexpr (PREC == P64) {
-        select_exit64(u1, u2, L.x, dt, axis, xe, L.amb);
+        select_exit64(u1, u2, L.x, dt, axis, xe, L.amb, Aa, upa);
     } else {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -758,7 +785,10 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
         const double tau = lim - L.t;
         if constexpr (OUT == O_SERIES) write_snaps<PREC, LAYOUT>(L, G, u1, u2, P, snap, lim, true);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) L.x[a] = adv<PREC>(u1[a], u2[a], L.x[a], tau, L.amb);
+        for (int a = 0; a < 3; ++a) {
+            if constexpr (PREC == P64) L.x[a] = adv64_au(Aa[a], upa[a], L.x[a], tau, L.amb);
+            else L.x[a] = adv<PREC>(u1[a], u2[a], L.x[a], tau, L.amb);
+        }
         L.t = lim;
         if constexpr (BATCHED) {
             if (next_step) {
@@ -795,8 +825,17 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
         const R v1b = (a2 == 1) ? u1[1] : u1[2];
         const R v2b = (a2 == 1) ? u2[1] : u2[2];
         const R xb = (a2 == 1) ? L.x[1] : L.x[2];
-        const R na = adv<PREC>(v1a, v2a, xa, dt, L.amb);
-        const R nb = adv<PREC>(v1b, v2b, xb, dt, L.amb);
+        R na, nb;
+        if constexpr (PREC == P64) {
+            const double Ax = (a1 == 0) ? Aa[0] : Aa[1], ux = (a1 == 0) ? upa[0] : upa[1];
+            const double Ay = (a2 == 1) ? Aa[1] : Aa[2], uy = (a2 == 1) ? upa[1] : upa[2];
+            (void)v1a, (void)v2a, (void)v1b, (void)v2b;
+            na = adv64_au(Ax, ux, xa, dt, L.amb);
+            nb = adv64_au(Ay, uy, xb, dt, L.amb);
+        } else {
+            na = adv<PREC>(v1a, v2a, xa, dt, L.amb);
+            nb = adv<PREC>(v1b, v2b, xb, dt, L.amb);
+        }
         L.x[0] = (axis == 0) ? xe : na;
         L.x[1] = (axis == 1) ? xe : ((a1 == 1) ? na : nb);
         L.x[2] = (axis == 2) ? xe : nb;
@@ -844,15 +883,19 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
         if (!(nfl & CF_ACTIVE)) return ST_INACTIVE_NB;
         nfl_sink = (nfl & CF_SINK) ? 1 : 0;
     }
-    if (axis == 0) {
-        L.i += step;
-        L.c += step;
-    } else if (axis == 1) {
-        L.j += step;
-        L.c += step * G.nx;
+    if constexpr (kTrackIJK<LAYOUT, OUT>) {
+        if (axis == 0) {
+            L.i += step;
+            L.c += step;
+        } else if (axis == 1) {
+            L.j += step;
+            L.c += step * G.nx;
+        } else {
+            L.k += step;
+            L.c += step * G.nx * G.ny;
+        }
     } else {
-        L.k += step;
-        L.c += step * G.nx * G.ny;
+        L.c += step * ((axis == 0) ? 1 : ((axis == 1) ? G.nx : G.nx * G.ny));
     }
     L.x[0] = (axis == 0) ? (R)1 - xe : L.x[0];
     L.x[1] = (axis == 1) ? (R)1 - xe : L.x[1];
