@@ -25,6 +25,23 @@ def pt():
     return require_gpu()
 
 
+def _check_invariants(out, p, label):
+    """Properties of every particle at any size: local coordinates in [0, 1], times never
+    before the release, a BOUNDARY particle on a face of its cell, crossings only added."""
+    for name in ("xi", "eta", "zeta"):
+        a = out[name]
+        assert ((a >= 0.0) & (a <= 1.0)).all(), (label, name)
+    tracked = (p.status == 0) | (p.status == 3)
+    assert (out["t"][tracked] >= p.t[tracked]).all(), label
+    assert (out["ncross"] >= p.ncross).all(), label
+    b = out["status"] == 1
+    on_face = np.zeros(b.sum(), dtype=bool)
+    for name in ("xi", "eta", "zeta"):
+        a = out[name][b]
+        on_face |= (a == 0.0) | (a == 1.0)
+    assert on_face.all(), (label, int((~on_face).sum()))
+
+
 def _check_counters(out, p):
     tracked, counts = tracked_counts(p.status, out["status"])
     s = out["summary"]
@@ -51,6 +68,7 @@ def test_c2_full_sampled(pt, sched):
     p = w.particles
     out = gpu_track(w.grids, p, **dict(BENCH_OPTS, schedule=sched))
     _check_counters(out, p)
+    _check_invariants(out, p, "C2")
     idx = sample_indices(p.n, 4000, seed=21)
     r = O.track(w.grids[0], p.subset(idx))
     compare(out, r, idx=idx, label="C2 sched %d" % sched, spacing=SP)
@@ -62,6 +80,7 @@ def test_c3_full_sampled(pt):
     p = w.particles
     out = gpu_track(w.grids, p, **BENCH_OPTS)
     _check_counters(out, p)
+    _check_invariants(out, p, "C3")
     idx = sample_indices(p.n, 3000, seed=31)
     r = O.track(w.grids[0], p.subset(idx))
     compare(out, r, idx=idx, label="C3", spacing=SP)
