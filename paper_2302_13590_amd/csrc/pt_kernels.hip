@@ -22,6 +22,13 @@
 // axis), apply the time limit, advance the other axes analytically, and
 // transfer to the neighbour.  Compiled with -ffp-contract=off: no FMA
 // contraction, so the FP64 path rounds exactly as written.
+//
+// Template arguments of both kernels: precision (FP64 / mixed), layout (face
+// arrays, packed structured records, quadtree records), output (endpoint,
+// timeseries positions, pathline records: the paper's three simulation types,
+// Methods "MODPATH") and whether a lane reads its grid from a table (batched
+// particle groups, or transient flow, where the table holds one field per time
+// step and the lane's index is its current step).
 #include <math.h>
 
 #include "pt_crmath.h"
