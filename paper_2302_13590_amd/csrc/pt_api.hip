@@ -122,7 +122,7 @@ struct pt_run {
     // per-run device tables (batched runs, snapshot times) and their pinned staging
     void* d_tables = nullptr;
     size_t d_tables_bytes = 0;
-    void* d_sort = nullptr;             // processing order [n] + bucket histogram
+    void* d_sort = nullptr;             // processing order [n] + ranks [n] + bucket histogram
     size_t d_sort_bytes = 0;
     void* d_scan = nullptr;             // pathline count pass: tile sums of the offset scan
     size_t d_scan_bytes = 0;
@@ -811,7 +811,7 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
         SP.nbuckets = (int32_t)(cells >> shift) + 1;
         SP.shift = shift;
         const size_t b_order = align_up(sizeof(int32_t) * (size_t)p->n, 256);
-        rc = ensure_sort(r, b_order + sizeof(unsigned) * (size_t)SP.nbuckets);
+        rc = ensure_sort(r, 2 * b_order + sizeof(unsigned) * (size_t)SP.nbuckets);
         if (rc != PT_OK) {
             destroy_run(r);
             return rc;
@@ -826,7 +826,8 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
                                                                   (total - b_base))
                                : nullptr;
         SP.order = static_cast<int32_t*>(r->d_sort);
-        SP.hist = reinterpret_cast<unsigned*>(static_cast<unsigned char*>(r->d_sort) + b_order);
+        SP.rank = reinterpret_cast<unsigned*>(static_cast<unsigned char*>(r->d_sort) + b_order);
+        SP.hist = reinterpret_cast<unsigned*>(static_cast<unsigned char*>(r->d_sort) + 2 * b_order);
         P.order = SP.order;
     }
     Counters* cptr = r->d_counters;

@@ -173,7 +173,8 @@ struct SortParams {
     int32_t shift;                  // bucket = global cell id >> shift
     int32_t nbuckets;
     int32_t pad;
-    unsigned* hist;                 // [nbuckets]
+    unsigned* hist;                 // [nbuckets] counts, then their exclusive prefix sums
+    unsigned* rank;                 // [n] rank of each particle within its bucket
     int32_t* order;                 // [n]
 };
 constexpr int kMaxBuckets = 1 << 16;

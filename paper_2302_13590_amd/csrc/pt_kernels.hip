@@ -1106,9 +1106,11 @@ __global__ void __launch_bounds__(256) k_sort_clear(SortParams S) {
         S.hist[q] = 0u;
 }
 
+// Bucket counts; each particle keeps the count its atomic returned (its rank in the bucket), so
+// the scatter needs no second round of atomics.
 __global__ void __launch_bounds__(256) k_sort_hist(SortParams S) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < S.n) atomicAdd(&S.hist[sort_bucket(S, p)], 1u);
+    if (p < S.n) S.rank[p] = atomicAdd(&S.hist[sort_bucket(S, p)], 1u);
 }
 
 // Exclusive prefix sum of the histogram in place, one workgroup of 1024 threads.
@@ -1137,10 +1139,7 @@ __global__ void __launch_bounds__(1024) k_sort_scan(SortParams S) {
 
 __global__ void __launch_bounds__(256) k_sort_scatter(SortParams S) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < S.n) {
-        const unsigned pos = atomicAdd(&S.hist[sort_bucket(S, p)], 1u);
-        S.order[pos] = (int32_t)p;
-    }
+    if (p < S.n) S.order[S.hist[sort_bucket(S, p)] + S.rank[p]] = (int32_t)p;
 }
 
 // ---------------------------------------------------------------------------------------------
