@@ -1,7 +1,12 @@
-"""Build properties of the tracking kernels (compiled for gfx950 on the CPU, not run): no
-kernel spills its lane state to scratch memory (dynamic indexing of the per-lane arrays or
-register spills would put every step's state in memory), and every tracking kernel keeps at
-least two waves per SIMD."""
+"""Build properties of the tracking kernels (compiled for gfx950 on the CPU, not run).
+
+The FP64 tracking kernels are built for four (static) and three (persistent) waves per SIMD;
+the register allocator then moves a few rarely used values (constants of the accurate phase of
+the correctly rounded functions) to scratch.  The tests bound that: no kernel other than the
+tracking kernels uses scratch at all, and no tracking kernel uses more than 96 bytes per lane
+(dynamic indexing of the per-lane arrays, which would put every step's state in memory, costs
+more: 184 bytes in the quadtree transfer before it was written with selects).  The occupancy
+floor keeps the wave counts the kernels were tuned for."""
 import os
 import re
 import shutil
@@ -42,13 +47,20 @@ def usage():
     return out
 
 
-def test_no_scratch(usage):
+MAX_TRACK_SCRATCH = 96
+
+
+def test_scratch_bounded(usage):
     spill = {k: v.get("ScratchSize", 0) for k, v in usage.items() if v.get("ScratchSize", 0) > 0}
-    assert not spill, spill
+    other = {k: b for k, b in spill.items() if "k_track_" not in k}
+    assert not other, other
+    big = {k: b for k, b in spill.items() if b > MAX_TRACK_SCRATCH}
+    assert not big, big
 
 
 def test_tracking_kernel_occupancy(usage):
     occ = {k: v.get("Occupancy", 0) for k, v in usage.items() if "k_track_" in k}
     assert len(occ) >= 30, sorted(occ)
-    low = {k: o for k, o in occ.items() if o < 2}
+    floor = {"k_track_static": 4, "k_track_persistent": 3}
+    low = {k: o for k, o in occ.items() if o < next(f for n, f in floor.items() if n in k)}
     assert not low, low
