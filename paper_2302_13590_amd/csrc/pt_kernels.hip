@@ -965,12 +965,22 @@ __device__ __forceinline__ void block_flush(BlockCounters& S, const TrackParams&
 }
 
 // ---------------------------------------------------------------------------------------------
-// Four waves per SIMD: the register allocator fits the FP64 kernels into 128 VGPRs (one hoisted
-// constant of the rare accurate phase goes to scratch) instead of 136, which allows three; the
-// fourth wave hides more of the record-gather latency (C2 -9%, C3 -10%).  Five waves (96 VGPRs)
-// spill live values in the loop and are slower; the FP32 kernels need fewer registers anyway.
+// Waves per SIMD the register allocator is asked to fit.  FP64: four (128 VGPRs, a constant of
+// the rare accurate phase in scratch) instead of three at 136 VGPRs -- the fourth wave hides
+// more of the dependent FP64 latency and the record gathers (C2 -9%, C3 -10%); five (96 VGPRs)
+// spill live loop values and are slower.  Mixed: eight for endpoint runs (C3 -5%), six for
+// timeseries and pathlines (C5 -4%; eight spills there).
+template <int PREC, int OUT>
+constexpr int kWavesStatic = PREC == P64 ? 4 : (OUT == O_END ? 8 : 6);
+// Persistent kernel: FP64 three (168 VGPRs instead of ~175, a few bytes of rarely used values in
+// scratch: C3 -20%, C2 -13%; four spill 110-230 bytes per lane and are slower); mixed six for
+// endpoint runs (C4 -7%), four otherwise.
+template <int PREC, int OUT>
+constexpr int kWavesPersistent = PREC == P64 ? 3 : (OUT == O_END ? 6 : 4);
+
 template <int PREC, int LAYOUT, int OUT, bool BATCHED>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_track_static(TrackParams P) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesStatic<PREC, OUT>)))
+k_track_static(TrackParams P) {
     __shared__ BlockShared<OUT == O_SERIES> S;
     const double* snap = block_setup<OUT == O_SERIES>(S, P);
     unsigned long long crossings = 0;
@@ -991,10 +1001,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     block_flush(S, P, crossings, L.amb, L.drop);
 }
 
-// Three waves per SIMD (168 VGPRs instead of ~175, a few bytes of rarely used values in
-// scratch): C3 -20%, C2 -13%.  Four waves (128 VGPRs) spill 110-230 bytes per lane and are slower.
 template <int PREC, int LAYOUT, int OUT, bool BATCHED>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) k_track_persistent(TrackParams P) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesPersistent<PREC, OUT>)))
+k_track_persistent(TrackParams P) {
     __shared__ BlockShared<OUT == O_SERIES> S;
     const double* snap = block_setup<OUT == O_SERIES>(S, P);
     unsigned long long crossings = 0;

@@ -1,8 +1,9 @@
 """Build properties of the tracking kernels (compiled for gfx950 on the CPU, not run).
 
-The FP64 tracking kernels are built for four (static) and three (persistent) waves per SIMD;
-the register allocator then moves a few rarely used values (constants of the accurate phase of
-the correctly rounded functions) to scratch.  The tests bound that: no kernel other than the
+The tracking kernels are built for a number of waves per SIMD (FP64: four static, three
+persistent; mixed: eight / six for endpoint runs, six / four otherwise); the register allocator
+then moves a few rarely used values (constants of the accurate phase of the correctly rounded
+functions) to scratch.  The tests bound that: no kernel other than the
 tracking kernels uses scratch at all, and no tracking kernel uses more than 96 bytes per lane
 (dynamic indexing of the per-lane arrays, which would put every step's state in memory, costs
 more: 184 bytes in the quadtree transfer before it was written with selects).  The occupancy
@@ -58,9 +59,19 @@ def test_scratch_bounded(usage):
     assert not big, big
 
 
+def _waves_floor(name):
+    """Waves per SIMD each tracking kernel is built for, from its template arguments
+    (precision 0 = FP64, 1 = mixed; output 0 = endpoint)."""
+    m = re.search(r"k_track_(static|persistent)ILi(\d)ELi(\d)ELi(\d)ELb(\d)", name)
+    assert m, name
+    kind, prec, out = m.group(1), int(m.group(2)), int(m.group(4))
+    if kind == "static":
+        return 4 if prec == 0 else (8 if out == 0 else 6)
+    return 3 if prec == 0 else (6 if out == 0 else 4)
+
+
 def test_tracking_kernel_occupancy(usage):
     occ = {k: v.get("Occupancy", 0) for k, v in usage.items() if "k_track_" in k}
     assert len(occ) >= 30, sorted(occ)
-    floor = {"k_track_static": 4, "k_track_persistent": 3}
-    low = {k: o for k, o in occ.items() if o < next(f for n, f in floor.items() if n in k)}
+    low = {k: o for k, o in occ.items() if o < _waves_floor(k)}
     assert not low, low
