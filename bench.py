@@ -288,7 +288,7 @@ def cpu_baseline(w, n_threads):
 
 
 # launch parameters of the scheduling study (the tuned C2/C3 shapes of each kernel)
-STUDY_LAUNCH = {"static": dict(block=128), "persistent": dict(block=256, refill=8, chunk=32, steps_per_refill=2)}
+STUDY_LAUNCH = {"static": dict(block=256), "persistent": dict(block=256, refill=1, chunk=32, steps_per_refill=2)}
 
 
 def scheduling_study(sigma2s, nps, reps):
