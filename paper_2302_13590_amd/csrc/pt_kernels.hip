@@ -192,19 +192,19 @@ __device__ __forceinline__ void select_exit64(const double (&u1)[3], const doubl
         if (feasible) est = (double)exit_estimate(e - xi[a], up, A, ue, unsure);
         E[a] = est;
     }
-    // candidate axis and its inputs (constant indices only: the arrays stay in registers)
+    // candidate axis, then its inputs by selects (constant indices only: the arrays stay in
+    // registers)
     int32_t w = -1;
-    double Ew = dinf(), w1 = 0.0, w2 = 0.0, wx = 0.0;
+    double Ew = dinf();
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (E[a] < Ew) {
-            Ew = E[a];
-            w = a;
-            w1 = u1[a];
-            w2 = u2[a];
-            wx = xi[a];
-        }
+        const bool lt = E[a] < Ew;
+        Ew = lt ? E[a] : Ew;
+        w = lt ? a : w;
     }
+    const double w1 = (w == 0) ? u1[0] : ((w == 1) ? u1[1] : u1[2]);
+    const double w2 = (w == 0) ? u2[0] : ((w == 1) ? u2[1] : u2[2]);
+    const double wx = (w == 0) ? xi[0] : ((w == 1) ? xi[1] : xi[2]);
     const double lim = Ew * (1.0 + kFilterMargin);
 #pragma unroll
     for (int a = 0; a < 3; ++a) unsure = unsure || (a != w && E[a] <= lim);
