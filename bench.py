@@ -267,6 +267,27 @@ def tuned_params(workload, precision, mode):
     return autotune.lookup(autotune.key(autotune.device_name(), workload, precision, mode))
 
 
+def final_state(case):
+    """Host copy of the final state of the last step run on `case` (status, time, path)."""
+    d = case.work.to_numpy()
+    return {k: d[k] for k in ("status", "t", "ncross", "path_hash")}
+
+
+def path_accuracy(mix, ref, t0):
+    """Cell-path agreement (same path hash and crossing count) of a mixed-precision result with an
+    FP64 one, and the relative error of the travel time of the particles that both brought to a
+    boundary.  mix, ref: final states of the same particles; t0: their release times."""
+    same = (mix["path_hash"] == ref["path_hash"]) & (mix["ncross"] == ref["ncross"])
+    done = (ref["status"] == 1) & (mix["status"] == 1)
+    tt = ref["t"][done] - t0[done]
+    pos = tt > 0
+    rel = np.abs((mix["t"][done] - t0[done])[pos] - tt[pos]) / tt[pos]
+    q = np.quantile(rel, [0.5, 0.99, 1.0]) if rel.size else [float("nan")] * 3
+    return {"particles": int(same.size), "path_agreement": round(float(same.mean()), 6),
+            "travel_time_rel_err": {"p50": float(q[0]), "p99": float(q[1]), "max": float(q[2]),
+                                    "particles": int(rel.size)}}
+
+
 def cpu_baseline(w, n_threads):
     """The oracle (plain FP64 CPU tracker) on the host cores, on a bounded sample."""
     from oracle import oracle as O
@@ -279,6 +300,7 @@ def cpu_baseline(w, n_threads):
     r = O.track(w.grids[0], sub, t_max=w.t_max, threads=n_threads)
     dt = time.perf_counter() - t0
     res["all_cores"] = dict(value=float(r.ncross.astype(np.int64).sum()) / dt, seconds=dt, particles=m)
+    res["sample_result"] = r
     m1 = min(p.n, 50_000)
     t0 = time.perf_counter()
     r1 = O.track(w.grids[0], p.subset(slice(0, m1)), t_max=w.t_max, threads=1)
@@ -397,6 +419,9 @@ def main():
 
     params, sched = launch(args.precision, args.schedule)
     primary = case.time(case.opts(args.precision, sched, **params), args.steps, args.warmup)
+    ref_state = final_state(case) if args.precision == "fp64" else None
+    mix_state = None
+    t_release = w.particles.t
     log("primary %s/%s %s: %.4g crossings/s, %.3f ms/step, kernel %.3f ms" % (
         args.precision, sched, params, primary["value"], primary["ms_per_step"], primary["kernel_ms"]))
     variants = {}
@@ -411,6 +436,13 @@ def main():
                 kernel_ms=round(r["kernel_ms"], 4), crossings_per_step=r["crossings_per_step"],
                 launch=p2, roofline_frac=roofline(r, n, prec, args.workload, s2, mode == "timeseries",
                                                   batched)["frac"])
+            if prec == "mixed" and ref_state is not None:
+                mix_state = final_state(case)
+                acc = path_accuracy(mix_state, ref_state, t_release)
+                acc["reference"] = "the FP64 run above (bitwise identical to the FP64 oracle in the parity tests)"
+                variants["%s_%s" % (prec, s2)]["accuracy"] = acc
+                log("mixed accuracy: path agreement %.4f, travel time rel. err. p50 %.2e p99 %.2e" % (
+                    acc["path_agreement"], acc["travel_time_rel_err"]["p50"], acc["travel_time_rel_err"]["p99"]))
             log("variant %s/%s: %.4g crossings/s" % (prec, s2, r["value"]))
         if mode == "endpoint":
             r = case.time_pathline(args.precision, sched, args.steps, args.warmup, **params)
@@ -471,6 +503,17 @@ def main():
                       % (cb["all_cores"]["particles"], cb["all_cores"]["seconds"], cb["one_core"]["particles"],
                          cb["one_core"]["value"], host_cpu_model()),
         }
+        if mix_state is not None and "variants" in out:
+            # the mixed-precision run against the oracle itself, on the oracle's sample
+            ro = cb["sample_result"]
+            m = ro.t.shape[0]
+            sub = {k: v[:m] for k, v in mix_state.items()}
+            acc = path_accuracy(sub, {"status": ro.status, "t": ro.t, "ncross": ro.ncross,
+                                      "path_hash": ro.path_hash}, t_release[:m])
+            acc["reference"] = "the FP64 oracle on the first %d particles" % m
+            for k, v in out["variants"].items():
+                if k.startswith("mixed_"):
+                    v["accuracy_vs_oracle"] = acc
     print(json.dumps(out), flush=True)
     return 0
 

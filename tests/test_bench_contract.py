@@ -34,3 +34,25 @@ def test_bench_line():
     rf = d["roofline"]
     assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
     assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-4
+
+
+def test_path_accuracy_report():
+    """The mixed-precision accuracy figures of the benchmark line: path agreement counts the
+    particles whose path hash and crossing count both match; travel times are compared only for
+    particles both runs brought to a boundary, relative to the FP64 travel time."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import bench
+    n = 8
+    ref = {"status": np.array([1, 1, 1, 1, 2, 1, 1, 3], np.int32), "t": np.arange(1.0, 9.0) + 10.0,
+           "ncross": np.full(n, 4, np.int32), "path_hash": np.arange(n, dtype=np.uint64)}
+    mix = {k: v.copy() for k, v in ref.items()}
+    mix["path_hash"][1] += np.uint64(1)          # different path
+    mix["ncross"][2] += 1                         # same hash, different count
+    mix["status"][5] = 3                          # did not reach the boundary
+    mix["t"][0] += 1e-3                           # travel time 1 -> 1.001
+    acc = bench.path_accuracy(mix, ref, t0=np.full(n, 10.0))
+    assert acc["particles"] == n and abs(acc["path_agreement"] - 6 / 8) < 1e-12
+    tr = acc["travel_time_rel_err"]
+    assert tr["particles"] == 5                   # statuses 1 in both: particles 0, 1, 2, 3, 6
+    assert abs(tr["max"] - 1e-3) < 1e-9 and tr["p50"] == 0.0
