@@ -364,6 +364,8 @@ def main():
     ap.add_argument("--only", action="store_true",
                     help="time only the primary variant (no other variants, no CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pathline", action="store_true",
+                    help="skip the pathline variant (its records take 40 B per crossing of device memory)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain elementwise copy of this many bytes (HBM-counter calibration)")
     ap.add_argument("--study", choices=["scheduling"],
@@ -444,7 +446,7 @@ def main():
                 log("mixed accuracy: path agreement %.4f, travel time rel. err. p50 %.2e p99 %.2e" % (
                     acc["path_agreement"], acc["travel_time_rel_err"]["p50"], acc["travel_time_rel_err"]["p99"]))
             log("variant %s/%s: %.4g crossings/s" % (prec, s2, r["value"]))
-        if mode == "endpoint":
+        if mode == "endpoint" and not args.no_pathline:
             r = case.time_pathline(args.precision, sched, args.steps, args.warmup, **params)
             variants["%s_pathline" % args.precision] = dict(
                 value=r["value"], ms_per_step=round(r["ms_per_step"], 4), count_ms=round(r["count_ms"], 4),
