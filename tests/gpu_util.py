@@ -123,3 +123,17 @@ def tracked_counts(before_status, after_status):
 
 
 INF = math.inf
+
+
+def bench_opts(wname, precision="fp64", mode="endpoint"):
+    """The launch the benchmark times for a workload: its autotuned parameters (schedule, block,
+    order, queue shape) on this device, packed layout, hipGraph; the persistent kernel with its
+    defaults where no tuned entry exists."""
+    from paper_2302_13590_amd import autotune
+    params = autotune.lookup(autotune.key(autotune.device_name(), wname, precision, mode)) or dict(schedule=2)
+    return dict(params, layout=2, use_graph=1, precision=0 if precision == "fp64" else 1)
+
+
+def other_schedule(opts):
+    """The other kernel, with its default launch shape."""
+    return dict(schedule=1 if opts["schedule"] == 2 else 2, layout=2, use_graph=1, precision=opts["precision"])

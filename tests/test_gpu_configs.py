@@ -12,11 +12,10 @@ import pytest
 from oracle import oracle as O
 from workloads import configs as C
 
-from .gpu_util import compare, gpu_track, require_gpu, sample_indices, tracked_counts
+from .gpu_util import bench_opts, compare, gpu_track, other_schedule, require_gpu, sample_indices, tracked_counts
 
 pytestmark = pytest.mark.gpu
 
-BENCH_OPTS = dict(schedule=2, layout=2, use_graph=1)   # the benchmark's FP64 launch
 SP = (10.0, 10.0, 2.0)                                 # cell sizes of C2-C5
 
 
@@ -54,7 +53,7 @@ def test_c1_full_closed_form(pt):
     w = C.c1()
     p = w.particles
     r = O.track(w.grids[0], p)
-    for kw in (dict(schedule=1, layout=1), dict(schedule=1, layout=2), BENCH_OPTS):
+    for kw in (dict(schedule=1, layout=1), dict(schedule=1, layout=2), dict(schedule=2, layout=2, use_graph=1)):
         out = gpu_track(w.grids, p, **kw)
         compare(out, r, label="C1 %s" % kw, spacing=(10.0, 10.0, 10.0))
         x0 = (p.cell % 40 + p.xi) * 10.0
@@ -62,23 +61,26 @@ def test_c1_full_closed_form(pt):
         assert np.max(np.abs(out["t"] - 1.2 * (400.0 - x0)) / out["t"]) <= 1e-12
 
 
-@pytest.mark.parametrize("sched", [1, 2])
-def test_c2_full_sampled(pt, sched):
+@pytest.mark.parametrize("launch", ["bench", "other"])
+def test_c2_full_sampled(pt, launch):
     w = C.c2()
     p = w.particles
-    out = gpu_track(w.grids, p, **dict(BENCH_OPTS, schedule=sched))
+    kw = bench_opts("C2")
+    if launch == "other":
+        kw = other_schedule(kw)
+    out = gpu_track(w.grids, p, **kw)
     _check_counters(out, p)
     _check_invariants(out, p, "C2")
     idx = sample_indices(p.n, 4000, seed=21)
     r = O.track(w.grids[0], p.subset(idx))
-    compare(out, r, idx=idx, label="C2 sched %d" % sched, spacing=SP)
-    print("C2 crossings", out["summary"]["crossings"], "kernel ms", out["summary"]["kernel_ms"])
+    compare(out, r, idx=idx, label="C2 %s" % kw, spacing=SP)
+    print("C2 %s crossings" % kw, out["summary"]["crossings"], "kernel ms", out["summary"]["kernel_ms"])
 
 
 def test_c3_full_sampled(pt):
     w = C.c3()
     p = w.particles
-    out = gpu_track(w.grids, p, **BENCH_OPTS)
+    out = gpu_track(w.grids, p, **bench_opts("C3"))
     _check_counters(out, p)
     _check_invariants(out, p, "C3")
     idx = sample_indices(p.n, 3000, seed=31)
@@ -92,7 +94,7 @@ def test_c3_full_sampled(pt):
 def test_c4_batched_full_sampled(pt):
     w = C.c4()
     p = w.particles
-    out = gpu_track(w.grids, p, group_offsets=w.group_offsets, group_grid=w.group_grid, **BENCH_OPTS)
+    out = gpu_track(w.grids, p, group_offsets=w.group_offsets, group_grid=w.group_grid, **bench_opts("C4"))
     _check_counters(out, p)
     idx = sample_indices(p.n, 3000, seed=41)
     grp = np.searchsorted(w.group_offsets, idx, side="right") - 1
@@ -106,7 +108,7 @@ def test_c4_batched_full_sampled(pt):
 def test_c5_timeseries_full_sampled(pt):
     w = C.c5()
     p = w.particles
-    out = gpu_track(w.grids, p, snap_times=w.snap_times, t_max=w.t_max, **BENCH_OPTS)
+    out = gpu_track(w.grids, p, snap_times=w.snap_times, t_max=w.t_max, **bench_opts("C5", mode="timeseries"))
     _check_counters(out, p)
     idx = sample_indices(p.n, 2000, seed=51)
     r = O.track(w.grids[0], p.subset(idx), snap_times=w.snap_times, t_max=w.t_max)
@@ -140,7 +142,7 @@ def test_mixed_precision_accuracy(pt, cfg):
     """Mixed FP32/FP64 against the FP64 oracle: reported, with loose sanity bounds."""
     w = C.c2() if cfg == "C2" else C.c5()
     p = w.particles
-    kw = dict(precision=1, schedule=2, layout=2, use_graph=1)
+    kw = bench_opts(cfg, "mixed", "timeseries" if w.snap_times is not None else "endpoint")
     if w.snap_times is not None:
         kw.update(snap_times=w.snap_times, t_max=w.t_max)
     out = gpu_track(w.grids, p, **kw)

@@ -15,7 +15,7 @@ from oracle import oracle as O
 from workloads import configs as C
 
 from . import helpers as H
-from .gpu_util import compare, require_gpu, sample_indices
+from .gpu_util import bench_opts, compare, require_gpu, sample_indices
 
 pytestmark = pytest.mark.gpu
 
@@ -257,7 +257,9 @@ def test_pathline_c2_full_sampled(pt, precision):
     handles = [pt.pt_load_grid(g) for g in w.grids]
     try:
         dp = pt.DeviceParticles.from_numpy(p, "cuda")
-        s, pl = pt.track_pathlines(handles, dp, precision=precision, schedule=1, layout=2, use_graph=1)
+        # the launch the benchmark's pathline variant times: the tuned FP64 endpoint launch of C2
+        kw = dict(bench_opts("C2"), precision=precision)
+        s, pl = pt.track_pathlines(handles, dp, **kw)
         m = s["path_records"]
         assert m == s["crossings"] and s["path_dropped"] == 0 and int(pl.offsets[-1]) == m
         _structure_on_device(pl, (100, 100, 10))

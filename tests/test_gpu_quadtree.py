@@ -11,7 +11,7 @@ from workloads import configs as C
 from workloads import quadtree as QT
 
 from . import helpers as H
-from .gpu_util import compare, gpu_track, require_gpu, sample_indices, tracked_counts
+from .gpu_util import bench_opts, compare, gpu_track, require_gpu, sample_indices, tracked_counts
 
 pytestmark = pytest.mark.gpu
 
@@ -127,7 +127,7 @@ def test_c7_full_sampled(pt):
     w = QT.c7()
     q = w.grids[0]
     p = w.particles
-    out = gpu_track([q], p, schedule=1, use_graph=1)
+    out = gpu_track([q], p, **bench_opts("C7"))
     s = out["summary"]
     assert s["crossings"] == int(out["ncross"].astype(np.int64).sum())
     idx = sample_indices(p.n, 3000, seed=81)

@@ -11,7 +11,7 @@ from workloads import configs as C
 
 from . import helpers as H
 from . import oracle_pins as PINS
-from .gpu_util import compare, gpu_track, require_gpu, sample_indices, tracked_counts
+from .gpu_util import bench_opts, compare, gpu_track, require_gpu, sample_indices, tracked_counts
 
 pytestmark = pytest.mark.gpu
 
@@ -165,8 +165,7 @@ def test_transient_option_errors(pt):
 def test_c6_full_sampled(pt):
     w = C.c6()
     p = w.particles
-    out = gpu_track(w.grids, p, tstep_end=w.tstep_end, stop_at_sink=w.stop_at_sink, schedule=1, layout=2,
-                    use_graph=1)
+    out = gpu_track(w.grids, p, tstep_end=w.tstep_end, stop_at_sink=w.stop_at_sink, **bench_opts("C6"))
     s = out["summary"]
     assert s["crossings"] == int(out["ncross"].astype(np.int64).sum())
     idx = sample_indices(p.n, 3000, seed=61)
