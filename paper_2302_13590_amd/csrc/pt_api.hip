@@ -122,7 +122,7 @@ struct pt_run {
     // per-run device tables (batched runs, snapshot times) and their pinned staging
     void* d_tables = nullptr;
     size_t d_tables_bytes = 0;
-    void* d_sort = nullptr;             // processing order [n] + ranks [n] + bucket histogram
+    void* d_sort = nullptr;             // order [n], ranks [n], buckets [n], histogram, tile sums
     size_t d_sort_bytes = 0;
     void* d_scan = nullptr;             // pathline count pass: tile sums of the offset scan
     size_t d_scan_bytes = 0;
@@ -665,9 +665,10 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     const int block = o->block ? o->block : 256;
     int grid;
     if (key.sched == S_STATIC) {
-        // a multiple of the die count: die d takes the d-th eighth of the slots
+        // a multiple of 8 chunks of blocks: chunks are dealt to the dies round robin
         const int64_t nb = std::max<int64_t>(1, (p->n + block - 1) / block);
-        grid = (int)((nb + kXcd - 1) / kXcd * kXcd);
+        const int64_t m = (int64_t)kXcd * kDieChunk;
+        grid = (int)((nb + m - 1) / m * m);
     } else {
         int per_cu = o->blocks_per_cu;
         if (!per_cu) {
@@ -810,8 +811,10 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
         while ((cells >> shift) >= kMaxBuckets) ++shift;
         SP.nbuckets = (int32_t)(cells >> shift) + 1;
         SP.shift = shift;
+        SP.ntiles = (int32_t)((SP.nbuckets + kScanTile - 1) / kScanTile);
         const size_t b_order = align_up(sizeof(int32_t) * (size_t)p->n, 256);
-        rc = ensure_sort(r, 2 * b_order + sizeof(unsigned) * (size_t)SP.nbuckets);
+        const size_t b_hist = align_up(sizeof(unsigned) * (size_t)SP.nbuckets, 256);
+        rc = ensure_sort(r, 3 * b_order + b_hist + sizeof(unsigned) * (size_t)SP.ntiles);
         if (rc != PT_OK) {
             destroy_run(r);
             return rc;
@@ -827,7 +830,9 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
                                : nullptr;
         SP.order = static_cast<int32_t*>(r->d_sort);
         SP.rank = reinterpret_cast<unsigned*>(static_cast<unsigned char*>(r->d_sort) + b_order);
-        SP.hist = reinterpret_cast<unsigned*>(static_cast<unsigned char*>(r->d_sort) + 2 * b_order);
+        SP.bucket = reinterpret_cast<unsigned*>(static_cast<unsigned char*>(r->d_sort) + 2 * b_order);
+        SP.hist = reinterpret_cast<unsigned*>(static_cast<unsigned char*>(r->d_sort) + 3 * b_order);
+        SP.part = reinterpret_cast<unsigned*>(static_cast<unsigned char*>(r->d_sort) + 3 * b_order + b_hist);
         P.order = SP.order;
     }
     Counters* cptr = r->d_counters;
@@ -836,10 +841,13 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     if (p->n > 0) {
         if (sort) {
             const unsigned nb = (unsigned)((p->n + 255) / 256);
-            seq.push_back({sort_clear_kernel(), dim3(std::min(256u, (unsigned)(SP.nbuckets + 255) / 256)),
+            seq.push_back({sort_clear_kernel(), dim3(std::min(2048u, (unsigned)(SP.nbuckets + 255) / 256)),
                            dim3(256), &SP, sizeof SP});
             seq.push_back({sort_hist_kernel(), dim3(nb), dim3(256), &SP, sizeof SP});
-            seq.push_back({sort_scan_kernel(), dim3(1), dim3(1024), &SP, sizeof SP});
+            seq.push_back({sort_scan_tiles_kernel(), dim3((unsigned)SP.ntiles), dim3(kScanBlock), &SP, sizeof SP});
+            seq.push_back({sort_scan_partials_kernel(), dim3(1), dim3(kScanBlock), &SP, sizeof SP});
+            if (SP.ntiles > 1)
+                seq.push_back({sort_scan_add_kernel(), dim3((unsigned)SP.ntiles), dim3(kScanBlock), &SP, sizeof SP});
             seq.push_back({sort_scatter_kernel(), dim3(nb), dim3(256), &SP, sizeof SP});
         }
         seq.push_back({fn, dim3(grid), dim3(block), &P, sizeof P});

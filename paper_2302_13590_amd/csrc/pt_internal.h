@@ -77,6 +77,7 @@ struct GridDev {
 };
 
 constexpr int kXcd = 8;   // accelerator complex dies; workgroup b runs on die b mod 8
+constexpr int kDieChunk = 16;   // static kernel: consecutive blocks of work dealt to one die at a time
 
 // Counters of a run (device), cleared by the reset kernel.
 struct Counters {
@@ -161,7 +162,8 @@ struct ScanParams {
     int64_t* head;     // element written 0 before v (path_off[0]); may be null
 };
 
-// Spatial ordering of particles by starting cell (counting sort into buckets of cells).
+// Spatial ordering of particles by starting cell (counting sort; one bucket per cell, or per run
+// of 2^shift cells on grids of more than kMaxBuckets cells).
 struct SortParams {
     int64_t n;
     const int32_t* cell;
@@ -172,12 +174,14 @@ struct SortParams {
     int32_t n_groups;
     int32_t shift;                  // bucket = global cell id >> shift
     int32_t nbuckets;
-    int32_t pad;
+    int32_t ntiles;                 // tiles of kScanTile buckets in the histogram scan
     unsigned* hist;                 // [nbuckets] counts, then their exclusive prefix sums
+    unsigned* part;                 // [ntiles] tile totals, then their exclusive prefix sums
+    unsigned* bucket;               // [n] bucket of each particle
     unsigned* rank;                 // [n] rank of each particle within its bucket
     int32_t* order;                 // [n]
 };
-constexpr int kMaxBuckets = 1 << 16;
+constexpr int64_t kMaxBuckets = (int64_t)1 << 24;   // histogram of at most 64 MB
 
 enum Precision { P64 = 0, PMIX = 1 };
 enum Layout { L_FACES = 1, L_CELL = 2, L_QUAD = 3 };
@@ -192,7 +196,9 @@ const void* track_kernel(const KernelKey& k);
 const void* reset_kernel();
 const void* sort_clear_kernel();
 const void* sort_hist_kernel();
-const void* sort_scan_kernel();
+const void* sort_scan_tiles_kernel();
+const void* sort_scan_partials_kernel();
+const void* sort_scan_add_kernel();
 const void* sort_scatter_kernel();
 const void* scan_tiles_kernel();
 const void* scan_partials_kernel();

@@ -987,10 +987,12 @@ k_track_static(TrackParams P) {
     Lane<PREC> L;
     L.amb = 0u;
     L.drop = 0u;
-    // die d = blockIdx.x mod 8 takes the d-th contiguous eighth of the slots (gridDim.x is a
-    // multiple of 8)
-    const int64_t per_die = (int64_t)gridDim.x / kXcd;
-    const int64_t blk = (int64_t)(blockIdx.x % kXcd) * per_die + blockIdx.x / kXcd;
+    // Block b runs on die b mod 8.  The slots are dealt to the dies in chunks of kDieChunk
+    // consecutive blocks, round robin: a die's concurrent blocks hold neighbouring particles
+    // (they share record lines in its L2), and every die sweeps the whole ordered work, so no die
+    // is left with a heavier part of it (gridDim.x is a multiple of 8 * kDieChunk).
+    const int64_t die = blockIdx.x % kXcd, j = blockIdx.x / kXcd;
+    const int64_t blk = ((j / kDieChunk) * kXcd + die) * kDieChunk + j % kDieChunk;
     const int64_t slot = blk * blockDim.x + threadIdx.x;
     if (slot < P.n) {
         L.pid = P.order ? (int64_t)P.order[slot] : slot;
@@ -1094,8 +1096,21 @@ __global__ void k_reset(Counters* c) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Spatial ordering: counting sort of the particles by the bucket of their starting cell.  The
-// order only changes which lanes and dies process which particles, never a result.
+// Block-wide inclusive scan of one value per thread (Hillis-Steele in LDS).
+__device__ __forceinline__ int64_t block_scan(int64_t* part, int64_t x) {
+    part[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+        const int64_t a = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += a;
+        __syncthreads();
+    }
+    return part[threadIdx.x];
+}
+
+// Spatial ordering: counting sort of the particles by their starting cell.  The order only
+// changes which lanes and dies process which particles, never a result.
 
 __device__ __forceinline__ uint32_t sort_bucket(const SortParams& S, int64_t p) {
     const int32_t c = S.cell[p];
@@ -1121,58 +1136,71 @@ __global__ void __launch_bounds__(256) k_sort_clear(SortParams S) {
         S.hist[q] = 0u;
 }
 
-// Bucket counts; each particle keeps the count its atomic returned (its rank in the bucket), so
-// the scatter needs no second round of atomics.
+// Bucket counts; each particle keeps its bucket and the count its atomic returned (its rank in
+// the bucket), so the scatter needs no second round of atomics.
 __global__ void __launch_bounds__(256) k_sort_hist(SortParams S) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < S.n) S.rank[p] = atomicAdd(&S.hist[sort_bucket(S, p)], 1u);
+    if (p < S.n) {
+        const uint32_t b = sort_bucket(S, p);
+        S.bucket[p] = b;
+        S.rank[p] = atomicAdd(&S.hist[b], 1u);
+    }
 }
 
-// Exclusive prefix sum of the histogram in place, one workgroup of 1024 threads.
-__global__ void __launch_bounds__(1024) k_sort_scan(SortParams S) {
-    __shared__ unsigned part[1024];
-    const int per = (S.nbuckets + 1023) / 1024;
-    const int lo = threadIdx.x * per;
-    const int hi = (lo + per < S.nbuckets) ? lo + per : S.nbuckets;
-    unsigned sum = 0;
-    for (int q = lo; q < hi; ++q) sum += S.hist[q];
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const unsigned v = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+// Exclusive prefix sum of the histogram in three passes: within each tile of kScanTile buckets
+// (tile totals to S.part), over the tile totals (one workgroup), then each tile adds the total of
+// the tiles before it.  Counts and sums stay below n < 2^31.
+__global__ void __launch_bounds__(kScanBlock) k_sort_scan_tiles(SortParams S) {
+    __shared__ int64_t part[kScanBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    unsigned v[kScanPer];
+    int64_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        v[q] = (base + q < S.nbuckets) ? S.hist[base + q] : 0u;
+        sum += v[q];
     }
-    unsigned run = part[threadIdx.x] - sum;
+    const int64_t incl = block_scan(part, sum);
+    int64_t run = incl - sum;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        if (base + q < S.nbuckets) S.hist[base + q] = (unsigned)run;
+        run += v[q];
+    }
+    if (threadIdx.x == kScanBlock - 1) S.part[blockIdx.x] = (unsigned)incl;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_sort_scan_partials(SortParams S) {
+    __shared__ int64_t part[kScanBlock];
+    const int per = (S.ntiles + kScanBlock - 1) / kScanBlock;
+    const int lo = (int)threadIdx.x * per;
+    const int hi = (lo + per < S.ntiles) ? lo + per : S.ntiles;
+    int64_t sum = 0;
+    for (int q = lo; q < hi; ++q) sum += S.part[q];
+    int64_t run = block_scan(part, sum) - sum;
     for (int q = lo; q < hi; ++q) {
-        const unsigned h = S.hist[q];
-        S.hist[q] = run;
+        const unsigned h = S.part[q];
+        S.part[q] = (unsigned)run;
         run += h;
     }
 }
 
+__global__ void __launch_bounds__(kScanBlock) k_sort_scan_add(SortParams S) {
+    const unsigned add = S.part[blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    for (int64_t q = threadIdx.x; q < kScanTile; q += kScanBlock)
+        if (base + q < S.nbuckets) S.hist[base + q] += add;
+}
+
 __global__ void __launch_bounds__(256) k_sort_scatter(SortParams S) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < S.n) S.order[S.hist[sort_bucket(S, p)] + S.rank[p]] = (int32_t)p;
+    if (p < S.n) S.order[S.hist[S.bucket[p]] + S.rank[p]] = (int32_t)p;
 }
 
 // ---------------------------------------------------------------------------------------------
 // Pathline offsets: inclusive prefix sum, in place, of the per-particle crossing counts written
 // by the count pass (v = path_offsets + 1), and path_offsets[0] = 0.
 
-// Block-wide inclusive scan of one value per thread (Hillis-Steele in LDS).
-__device__ __forceinline__ int64_t block_scan(int64_t* part, int64_t x) {
-    part[threadIdx.x] = x;
-    __syncthreads();
-    for (int off = 1; off < kScanBlock; off <<= 1) {
-        const int64_t a = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0;
-        __syncthreads();
-        part[threadIdx.x] += a;
-        __syncthreads();
-    }
-    return part[threadIdx.x];
-}
 
 // Tile b (kScanTile elements): scan within the tile, tile total to part[b].
 __global__ void __launch_bounds__(kScanBlock) k_scan_tiles(ScanParams S) {
@@ -1354,7 +1382,9 @@ const void* track_kernel(const KernelKey& k) {
 const void* reset_kernel() { return reinterpret_cast<const void*>(&k_reset); }
 const void* sort_clear_kernel() { return reinterpret_cast<const void*>(&k_sort_clear); }
 const void* sort_hist_kernel() { return reinterpret_cast<const void*>(&k_sort_hist); }
-const void* sort_scan_kernel() { return reinterpret_cast<const void*>(&k_sort_scan); }
+const void* sort_scan_tiles_kernel() { return reinterpret_cast<const void*>(&k_sort_scan_tiles); }
+const void* sort_scan_partials_kernel() { return reinterpret_cast<const void*>(&k_sort_scan_partials); }
+const void* sort_scan_add_kernel() { return reinterpret_cast<const void*>(&k_sort_scan_add); }
 const void* sort_scatter_kernel() { return reinterpret_cast<const void*>(&k_sort_scatter); }
 const void* scan_tiles_kernel() { return reinterpret_cast<const void*>(&k_scan_tiles); }
 const void* scan_partials_kernel() { return reinterpret_cast<const void*>(&k_scan_partials); }
