@@ -223,7 +223,8 @@ typedef struct {
     int32_t chunk;                /* persistent: particles a wave claims from the device queue  *
                                    * per atomic, >= 1, 0 = default (64)                          */
     int32_t sort;                 /* PT_SORT_*: processing order (never changes a result); the   *
-                                   * ordered work is split into one contiguous part per die     */
+                                   * static kernel deals the ordered work to the dies in chunks  *
+                                   * of consecutive blocks                                      */
     /* PT_PATHLINE.  A pathline is the release point (the input state), one record per cell
      * crossing made in this call, in crossing order, and the final state.  Records are stored
      * particle by particle (CSR): those of particle p fill path_records[path_offsets[p] ..
