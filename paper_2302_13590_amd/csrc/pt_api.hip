@@ -229,7 +229,8 @@ struct Launch {
     const void* fn;
     dim3 grid, block;
     void* arg;
-    size_t bytes;   // size of *arg
+    size_t bytes;       // size of *arg
+    size_t lds = 0;     // dynamic LDS bytes per block
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -283,9 +284,9 @@ void free_grid(pt_grid* g) {
 }
 
 // Launch one kernel through the HIP module-less API.
-hipError_t launch(const void* fn, dim3 grid, dim3 block, void* arg, hipStream_t s) {
+hipError_t launch(const void* fn, dim3 grid, dim3 block, void* arg, size_t lds, hipStream_t s) {
     void* args[] = {arg};
-    return hipLaunchKernel(fn, grid, block, args, 0, s);
+    return hipLaunchKernel(fn, grid, block, args, lds, s);
 }
 
 }  // namespace
@@ -396,7 +397,7 @@ int pt_load_grid(const pt_grid_desc* d, void* hip_stream, pt_grid** out) {
     B.balance_tol = d->balance_tol;
     B.err = static_cast<int*>(err);
     if (e == hipSuccess)
-        e = launch(build_kernel(), dim3((unsigned)((ncell + 255) / 256)), dim3(256), &B, s);
+        e = launch(build_kernel(), dim3((unsigned)((ncell + 255) / 256)), dim3(256), &B, 0, s);
     int herr[4] = {0, 0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(herr, err, sizeof herr, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -507,7 +508,7 @@ int pt_load_quad_grid(const pt_quad_desc* d, void* hip_stream, pt_grid** out) {
     B.balance_tol = d->balance_tol;
     B.err = static_cast<int*>(err);
     if (e == hipSuccess)
-        e = launch(build_quad_kernel(), dim3((unsigned)((ncell + 255) / 256)), dim3(256), &B, s);
+        e = launch(build_quad_kernel(), dim3((unsigned)((ncell + 255) / 256)), dim3(256), &B, 0, s);
     int herr[4] = {0, 0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(herr, err, sizeof herr, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -850,7 +851,11 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
                 seq.push_back({sort_scan_add_kernel(), dim3((unsigned)SP.ntiles), dim3(kScanBlock), &SP, sizeof SP});
             seq.push_back({sort_scatter_kernel(), dim3(nb), dim3(256), &SP, sizeof SP});
         }
-        seq.push_back({fn, dim3(grid), dim3(block), &P, sizeof P});
+        // the FP64 static timeseries kernels on packed layouts keep one deferred-snapshot slot
+        // per thread in dynamic LDS
+        const bool snap_slots = key.out == O_SERIES && key.precision == P64 && key.sched == S_STATIC &&
+                                key.layout != L_FACES;
+        seq.push_back({fn, dim3(grid), dim3(block), &P, sizeof P, snap_slots ? sizeof(SnapJob) * (size_t)block : 0});
         if (path_count) seq.push_back({scan_tiles_kernel(), dim3((unsigned)SC.ntiles), dim3(kScanBlock), &SC, sizeof SC});
     }
     if (path_count) {
@@ -861,14 +866,14 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     hipError_t e = hipEventRecord(r->ev0, s);
     if (e == hipSuccess) {
         if (o->use_graph) {
-            // key: every launch's function, shape and argument bytes
+            // key: every launch's function, shape, dynamic LDS and argument bytes
             std::vector<unsigned char> gkey;
             for (const Launch& L : seq) {
                 const size_t bytes = L.bytes;
                 const unsigned char* a = static_cast<const unsigned char*>(L.arg);
                 const unsigned char* f = reinterpret_cast<const unsigned char*>(&L.fn);
                 gkey.insert(gkey.end(), f, f + sizeof L.fn);
-                const unsigned dims[2] = {L.grid.x, L.block.x};
+                const unsigned dims[3] = {L.grid.x, L.block.x, (unsigned)L.lds};
                 const unsigned char* d = reinterpret_cast<const unsigned char*>(dims);
                 gkey.insert(gkey.end(), d, d + sizeof dims);
                 gkey.insert(gkey.end(), a, a + bytes);
@@ -891,6 +896,7 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
                     kp.gridDim = seq[q].grid;
                     kp.blockDim = seq[q].block;
                     kp.kernelParams = args;
+                    kp.sharedMemBytes = (unsigned)seq[q].lds;
                     hipGraphNode_t node = nullptr;
                     e = hipGraphAddKernelNode(&node, gr, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
                     prev = node;
@@ -907,7 +913,7 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
             if (e == hipSuccess) e = hipGraphLaunch(r->exec, s);
         } else {
             for (size_t q = 0; e == hipSuccess && q < seq.size(); ++q)
-                e = launch(seq[q].fn, seq[q].grid, seq[q].block, seq[q].arg, s);
+                e = launch(seq[q].fn, seq[q].grid, seq[q].block, seq[q].arg, seq[q].lds, s);
         }
     }
     if (e == hipSuccess) e = hipEventRecord(r->ev1, s);

@@ -231,4 +231,16 @@ struct BuildQuadParams {
 
 constexpr int kMaxSnapLds = 1024;
 
+// Slot of one lane for deferred snapshots (FP64 static kernel, timeseries, packed layouts): the
+// step-start state and the range [ks0, ks0 + cnt) of snapshot indices; cnt = 0 when free.  The
+// kernel takes blockDim.x slots of dynamic LDS.
+struct SnapJob {
+    double x[3];
+    double t;
+    int32_t c, i, j, k;
+    int32_t g, pid, ks0, cnt;
+    int32_t start, pad;   // first pair index of the slot in a flush
+};
+static_assert(sizeof(SnapJob) == 72, "SnapJob layout");
+
 }  // namespace pt

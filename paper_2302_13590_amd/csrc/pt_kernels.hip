@@ -490,6 +490,21 @@ __device__ __forceinline__ void cell_xyz(const GridDev& G, int32_t c, int32_t i,
     }
 }
 
+// Position at snapshot time s of a particle whose step started at time t in cell c (i, j, k)
+// with local coordinates x: tau = s - t on every axis.
+template <int PREC, int LAYOUT>
+__device__ __forceinline__ void eval_snap(const GridDev& G, const typename Real<PREC>::T (&u1)[3],
+                                          const typename Real<PREC>::T (&u2)[3],
+                                          const typename Real<PREC>::T (&x)[3], double t, int32_t c,
+                                          int32_t i, int32_t j, int32_t k, double s, double* out,
+                                          unsigned& amb) {
+    const double tau = s - t;
+    const double a = (double)adv<PREC>(u1[0], u2[0], x[0], tau, amb);
+    const double b = (double)adv<PREC>(u1[1], u2[1], x[1], tau, amb);
+    const double d = (double)adv<PREC>(u1[2], u2[2], x[2], tau, amb);
+    cell_xyz<LAYOUT>(G, c, i, j, k, a, b, d, out);
+}
+
 // Positions at the snapshot times s with s < to (or s <= to when closed), evaluated from the
 // state at the start of the step with tau = s - t.
 template <int PREC, int LAYOUT>
@@ -502,14 +517,97 @@ __device__ __forceinline__ void write_snaps(Lane<PREC>& L, const GridDev& G,
     while (L.ks < P.n_snap) {
         const double s = L.s_next;
         if (closed ? !(s <= to) : !(s < to)) break;
-        const double tau = s - L.t;
-        const double a = (double)adv<PREC>(u1[0], u2[0], L.x[0], tau, L.amb);
-        const double b = (double)adv<PREC>(u1[1], u2[1], L.x[1], tau, L.amb);
-        const double d = (double)adv<PREC>(u1[2], u2[2], L.x[2], tau, L.amb);
-        cell_xyz<LAYOUT>(G, L.c, L.i, L.j, L.k, a, b, d, row + 3 * (int64_t)L.ks);
+        eval_snap<PREC, LAYOUT>(G, u1, u2, L.x, L.t, L.c, L.i, L.j, L.k, s, row + 3 * (int64_t)L.ks, L.amb);
         ++L.ks;
         L.s_next = (L.ks < P.n_snap) ? snap[L.ks] : dinf();
     }
+}
+
+// Deferred snapshots (static kernel, timeseries, packed layouts).  In a wave, only the few lanes
+// whose step holds a snapshot time would run the snapshot arithmetic at that step, while the
+// others wait.  Instead a lane records its step-start state and snapshot range in its LDS slot;
+// once kSnapFlush lanes of the wave have a pending slot (or no lane is left tracking), the wave
+// evaluates all pending snapshots together, each lane taking one (slot, snapshot) pair.  Each
+// snapshot is the same function of the same state, so the results do not change.
+constexpr int kSnapFlush = 32;
+
+// Ordering of the LDS slots between the lanes of one wave.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The snapshots of a step ending at `to` (open interval): into the lane's slot when it is free,
+// else evaluated at once.
+template <int LAYOUT>
+__device__ __forceinline__ void queue_snaps(Lane<P64>& L, const GridDev& G, const double (&u1)[3],
+                                            const double (&u2)[3], const TrackParams& P, const double* snap,
+                                            double to, SnapJob* job) {
+    const int32_t ks0 = L.ks;
+    while (L.ks < P.n_snap && L.s_next < to) {
+        ++L.ks;
+        L.s_next = (L.ks < P.n_snap) ? snap[L.ks] : dinf();
+    }
+    const int32_t cnt = L.ks - ks0;
+    if (cnt == 0) return;
+    if (job->cnt == 0) {
+        job->x[0] = L.x[0];
+        job->x[1] = L.x[1];
+        job->x[2] = L.x[2];
+        job->t = L.t;
+        job->c = L.c;
+        job->i = L.i;
+        job->j = L.j;
+        job->k = L.k;
+        job->g = L.g;
+        job->pid = (int32_t)L.pid;
+        job->ks0 = ks0;
+        job->cnt = cnt;
+    } else {
+        double* row = P.snap_xyz + L.pid * (int64_t)P.n_snap * 3;
+        for (int32_t q = ks0; q < L.ks; ++q)
+            eval_snap<P64, LAYOUT>(G, u1, u2, L.x, L.t, L.c, L.i, L.j, L.k, snap[q], row + 3 * (int64_t)q, L.amb);
+    }
+}
+
+// All lanes of the wave: evaluate every pending snapshot of the wave's 64 slots W and free them.
+template <int LAYOUT, bool BATCHED>
+__device__ __forceinline__ void flush_snaps(SnapJob* W, const TrackParams& P, const double* snap, unsigned& amb) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const int cnt = W[lane].cnt;
+    int incl = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+    }
+    const int total = __shfl(incl, 63, 64);
+    W[lane].start = incl - cnt;
+    wave_sync();
+    for (int q = lane; q < total; q += 64) {
+        // the slot holding pair q: the last one whose first pair is at most q (it has cnt > 0)
+        int lo = 0, hi = 64;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (W[mid].start <= q) lo = mid;
+            else hi = mid;
+        }
+        const SnapJob& J = W[lo];
+        const GridDev& G = grid_of<BATCHED>(P, J.g);
+        double u1[3], u2[3], x[3];
+        int32_t fl;
+        load_rec<P64>(G, J.c, P.sign, u1, u2, fl);
+        x[0] = J.x[0];
+        x[1] = J.x[1];
+        x[2] = J.x[2];
+        const int32_t ks = J.ks0 + (q - J.start);
+        eval_snap<P64, LAYOUT>(G, u1, u2, x, J.t, J.c, J.i, J.j, J.k, snap[ks],
+                                P.snap_xyz + ((int64_t)J.pid * P.n_snap + ks) * 3, amb);
+    }
+    wave_sync();
+    W[lane].cnt = 0;
+    wave_sync();
 }
 
 template <int PREC>
@@ -731,10 +829,11 @@ __device__ int32_t quad_transfer(Lane<PREC>& L, const GridDev& G, const TrackPar
     return 0;
 }
 
-// One cell crossing (S1-S7).  Returns 0 to continue, or the final status.
+// One cell crossing (S1-S7).  Returns 0 to continue, or the final status.  `job`: the lane's
+// slot for deferred snapshots, or null to write them at once.
 template <int PREC, int LAYOUT, int OUT, bool BATCHED>
 __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& P, const double* snap,
-                                              unsigned long long& crossings) {
+                                              unsigned long long& crossings, SnapJob* job = nullptr) {
     using R = typename Real<PREC>::T;
     const GridDev& G = grid_of<BATCHED>(P, L.g);
     R u1[3], u2[3];
@@ -822,7 +921,14 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
     const int32_t step = hi ? 1 : -1;
 
     // advance to the exit face: the two other axes move analytically
-    if constexpr (OUT == O_SERIES) write_snaps<PREC, LAYOUT>(L, G, u1, u2, P, snap, t_exit, false);
+    if constexpr (OUT == O_SERIES) {
+        if constexpr (PREC == P64) {
+            if (job) queue_snaps<LAYOUT>(L, G, u1, u2, P, snap, t_exit, job);
+            else write_snaps<PREC, LAYOUT>(L, G, u1, u2, P, snap, t_exit, false);
+        } else {
+            write_snaps<PREC, LAYOUT>(L, G, u1, u2, P, snap, t_exit, false);
+        }
+    }
     {
         const int a1 = (axis == 0) ? 1 : 0;
         const int a2 = (axis == 2) ? 1 : 2;
@@ -994,11 +1100,36 @@ k_track_static(TrackParams P) {
     const int64_t die = blockIdx.x % kXcd, j = blockIdx.x / kXcd;
     const int64_t blk = ((j / kDieChunk) * kXcd + die) * kDieChunk + j % kDieChunk;
     const int64_t slot = blk * blockDim.x + threadIdx.x;
-    if (slot < P.n) {
-        L.pid = P.order ? (int64_t)P.order[slot] : slot;
-        int32_t st = begin<PREC, LAYOUT, OUT, BATCHED>(L, P, snap);
-        while (st == 0) st = track_step<PREC, LAYOUT, OUT, BATCHED>(L, P, snap, crossings);
+    if constexpr (OUT == O_SERIES && kPacked<LAYOUT> && PREC == P64) {
+        // FP64 timeseries: the wave steps its lanes together so that it can evaluate the deferred
+        // snapshots of all of them at once (the FP32 snapshot arithmetic is cheap enough that the
+        // slots' LDS, which costs the mixed kernel two of its six waves per SIMD, does not pay)
+        extern __shared__ SnapJob jobs[];   // blockDim.x slots of dynamic LDS
+        SnapJob* W = jobs + (threadIdx.x & ~63u);
+        jobs[threadIdx.x].cnt = 0;
+        wave_sync();
+        int32_t st = ST_SKIP;
+        if (slot < P.n) {
+            L.pid = P.order ? (int64_t)P.order[slot] : slot;
+            st = begin<PREC, LAYOUT, OUT, BATCHED>(L, P, snap);
+        }
+        for (;;) {
+            if (st == 0) st = track_step<PREC, LAYOUT, OUT, BATCHED>(L, P, snap, crossings, &jobs[threadIdx.x]);
+            wave_sync();
+            const unsigned long long pend = __ballot(jobs[threadIdx.x].cnt > 0);
+            const unsigned long long live = __ballot(st == 0);
+            if (pend != 0ull && (__popcll(pend) >= kSnapFlush || live == 0ull))
+                flush_snaps<LAYOUT, BATCHED>(W, P, snap, L.amb);
+            if (live == 0ull) break;
+        }
         if (st > 0) finish<PREC, LAYOUT, OUT, BATCHED>(L, st, P, S.hist);
+    } else {
+        if (slot < P.n) {
+            L.pid = P.order ? (int64_t)P.order[slot] : slot;
+            int32_t st = begin<PREC, LAYOUT, OUT, BATCHED>(L, P, snap);
+            while (st == 0) st = track_step<PREC, LAYOUT, OUT, BATCHED>(L, P, snap, crossings);
+            if (st > 0) finish<PREC, LAYOUT, OUT, BATCHED>(L, st, P, S.hist);
+        }
     }
     block_flush(S, P, crossings, L.amb, L.drop);
 }
