@@ -851,11 +851,11 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
                 seq.push_back({sort_scan_add_kernel(), dim3((unsigned)SP.ntiles), dim3(kScanBlock), &SP, sizeof SP});
             seq.push_back({sort_scatter_kernel(), dim3(nb), dim3(256), &SP, sizeof SP});
         }
-        // the FP64 static timeseries kernels on packed layouts keep one deferred-snapshot slot
-        // per thread in dynamic LDS
-        const bool snap_slots = key.out == O_SERIES && key.precision == P64 && key.sched == S_STATIC &&
-                                key.layout != L_FACES;
-        seq.push_back({fn, dim3(grid), dim3(block), &P, sizeof P, snap_slots ? sizeof(SnapJob) * (size_t)block : 0});
+        // the static timeseries kernels on packed layouts keep one deferred-snapshot slot per
+        // thread in dynamic LDS
+        const bool snap_slots = key.out == O_SERIES && key.sched == S_STATIC && key.layout != L_FACES;
+        const size_t slot = key.precision == P64 ? sizeof(SnapJob<double>) : sizeof(SnapJob<float>);
+        seq.push_back({fn, dim3(grid), dim3(block), &P, sizeof P, snap_slots ? slot * (size_t)block : 0});
         if (path_count) seq.push_back({scan_tiles_kernel(), dim3((unsigned)SC.ntiles), dim3(kScanBlock), &SC, sizeof SC});
     }
     if (path_count) {

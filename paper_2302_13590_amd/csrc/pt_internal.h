@@ -231,16 +231,17 @@ struct BuildQuadParams {
 
 constexpr int kMaxSnapLds = 1024;
 
-// Slot of one lane for deferred snapshots (FP64 static kernel, timeseries, packed layouts): the
+// Slot of one lane for deferred snapshots (static kernel, timeseries, packed layouts): the
 // step-start state and the range [ks0, ks0 + cnt) of snapshot indices; cnt = 0 when free.  The
-// kernel takes blockDim.x slots of dynamic LDS.
+// kernel takes blockDim.x slots of dynamic LDS.  R: the precision of the local coordinates.
+template <typename R>
 struct SnapJob {
-    double x[3];
     double t;
+    R x[3];
     int32_t c, i, j, k;
     int32_t g, pid, ks0, cnt;
-    int32_t start, pad;   // first pair index of the slot in a flush
+    int32_t start;        // first pair index of the slot in a flush
 };
-static_assert(sizeof(SnapJob) == 72, "SnapJob layout");
+static_assert(sizeof(SnapJob<double>) == 72 && sizeof(SnapJob<float>) == 56, "SnapJob layout");
 
 }  // namespace pt

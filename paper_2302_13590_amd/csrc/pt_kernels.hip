@@ -540,10 +540,12 @@ __device__ __forceinline__ void wave_sync() {
 
 // The snapshots of a step ending at `to` (open interval): into the lane's slot when it is free,
 // else evaluated at once.
-template <int LAYOUT>
-__device__ __forceinline__ void queue_snaps(Lane<P64>& L, const GridDev& G, const double (&u1)[3],
-                                            const double (&u2)[3], const TrackParams& P, const double* snap,
-                                            double to, SnapJob* job) {
+template <int PREC, int LAYOUT>
+__device__ __forceinline__ void queue_snaps(Lane<PREC>& L, const GridDev& G,
+                                            const typename Real<PREC>::T (&u1)[3],
+                                            const typename Real<PREC>::T (&u2)[3], const TrackParams& P,
+                                            const double* snap, double to,
+                                            SnapJob<typename Real<PREC>::T>* job) {
     const int32_t ks0 = L.ks;
     while (L.ks < P.n_snap && L.s_next < to) {
         ++L.ks;
@@ -567,13 +569,15 @@ __device__ __forceinline__ void queue_snaps(Lane<P64>& L, const GridDev& G, cons
     } else {
         double* row = P.snap_xyz + L.pid * (int64_t)P.n_snap * 3;
         for (int32_t q = ks0; q < L.ks; ++q)
-            eval_snap<P64, LAYOUT>(G, u1, u2, L.x, L.t, L.c, L.i, L.j, L.k, snap[q], row + 3 * (int64_t)q, L.amb);
+            eval_snap<PREC, LAYOUT>(G, u1, u2, L.x, L.t, L.c, L.i, L.j, L.k, snap[q], row + 3 * (int64_t)q, L.amb);
     }
 }
 
 // All lanes of the wave: evaluate every pending snapshot of the wave's 64 slots W and free them.
-template <int LAYOUT, bool BATCHED>
-__device__ __forceinline__ void flush_snaps(SnapJob* W, const TrackParams& P, const double* snap, unsigned& amb) {
+template <int PREC, int LAYOUT, bool BATCHED>
+__device__ __forceinline__ void flush_snaps(SnapJob<typename Real<PREC>::T>* W, const TrackParams& P,
+                                            const double* snap, unsigned& amb) {
+    using R = typename Real<PREC>::T;
     const int lane = (int)(threadIdx.x & 63u);
     const int cnt = W[lane].cnt;
     int incl = cnt;
@@ -593,16 +597,16 @@ __device__ __forceinline__ void flush_snaps(SnapJob* W, const TrackParams& P, co
             if (W[mid].start <= q) lo = mid;
             else hi = mid;
         }
-        const SnapJob& J = W[lo];
+        const SnapJob<R>& J = W[lo];
         const GridDev& G = grid_of<BATCHED>(P, J.g);
-        double u1[3], u2[3], x[3];
+        R u1[3], u2[3], x[3];
         int32_t fl;
-        load_rec<P64>(G, J.c, P.sign, u1, u2, fl);
+        load_rec<PREC>(G, J.c, P.sign, u1, u2, fl);
         x[0] = J.x[0];
         x[1] = J.x[1];
         x[2] = J.x[2];
         const int32_t ks = J.ks0 + (q - J.start);
-        eval_snap<P64, LAYOUT>(G, u1, u2, x, J.t, J.c, J.i, J.j, J.k, snap[ks],
+        eval_snap<PREC, LAYOUT>(G, u1, u2, x, J.t, J.c, J.i, J.j, J.k, snap[ks],
                                 P.snap_xyz + ((int64_t)J.pid * P.n_snap + ks) * 3, amb);
     }
     wave_sync();
@@ -833,7 +837,8 @@ __device__ int32_t quad_transfer(Lane<PREC>& L, const GridDev& G, const TrackPar
 // slot for deferred snapshots, or null to write them at once.
 template <int PREC, int LAYOUT, int OUT, bool BATCHED>
 __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& P, const double* snap,
-                                              unsigned long long& crossings, SnapJob* job = nullptr) {
+                                              unsigned long long& crossings,
+                                              SnapJob<typename Real<PREC>::T>* job = nullptr) {
     using R = typename Real<PREC>::T;
     const GridDev& G = grid_of<BATCHED>(P, L.g);
     R u1[3], u2[3];
@@ -922,12 +927,8 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
 
     // advance to the exit face: the two other axes move analytically
     if constexpr (OUT == O_SERIES) {
-        if constexpr (PREC == P64) {
-            if (job) queue_snaps<LAYOUT>(L, G, u1, u2, P, snap, t_exit, job);
-            else write_snaps<PREC, LAYOUT>(L, G, u1, u2, P, snap, t_exit, false);
-        } else {
-            write_snaps<PREC, LAYOUT>(L, G, u1, u2, P, snap, t_exit, false);
-        }
+        if (job) queue_snaps<PREC, LAYOUT>(L, G, u1, u2, P, snap, t_exit, job);
+        else write_snaps<PREC, LAYOUT>(L, G, u1, u2, P, snap, t_exit, false);
     }
     {
         const int a1 = (axis == 0) ? 1 : 0;
@@ -1034,7 +1035,7 @@ template <> struct BlockShared<true> : BlockCounters {
     double snap[kMaxSnapLds];
 };
 
-template <bool TS>
+template <int PREC, bool TS>
 __device__ __forceinline__ const double* block_setup(BlockShared<TS>& S, const TrackParams& P) {
     if (threadIdx.x < 8) S.hist[threadIdx.x] = 0u;
     if (threadIdx.x == 0) {
@@ -1042,7 +1043,7 @@ __device__ __forceinline__ const double* block_setup(BlockShared<TS>& S, const T
         S.amb = 0u;
         S.drop = 0u;
     }
-    ptcr::lds_tables_init();
+    if constexpr (PREC == P64) ptcr::lds_tables_init();   // the FP32 path has no table lookups
     const double* snap = P.snap_times;
     if constexpr (TS) {
         if (P.n_snap <= kMaxSnapLds) {
@@ -1088,7 +1089,7 @@ template <int PREC, int LAYOUT, int OUT, bool BATCHED>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesStatic<PREC, OUT>)))
 k_track_static(TrackParams P) {
     __shared__ BlockShared<OUT == O_SERIES> S;
-    const double* snap = block_setup<OUT == O_SERIES>(S, P);
+    const double* snap = block_setup<PREC, OUT == O_SERIES>(S, P);
     unsigned long long crossings = 0;
     Lane<PREC> L;
     L.amb = 0u;
@@ -1100,12 +1101,13 @@ k_track_static(TrackParams P) {
     const int64_t die = blockIdx.x % kXcd, j = blockIdx.x / kXcd;
     const int64_t blk = ((j / kDieChunk) * kXcd + die) * kDieChunk + j % kDieChunk;
     const int64_t slot = blk * blockDim.x + threadIdx.x;
-    if constexpr (OUT == O_SERIES && kPacked<LAYOUT> && PREC == P64) {
-        // FP64 timeseries: the wave steps its lanes together so that it can evaluate the deferred
-        // snapshots of all of them at once (the FP32 snapshot arithmetic is cheap enough that the
-        // slots' LDS, which costs the mixed kernel two of its six waves per SIMD, does not pay)
-        extern __shared__ SnapJob jobs[];   // blockDim.x slots of dynamic LDS
-        SnapJob* W = jobs + (threadIdx.x & ~63u);
+    if constexpr (OUT == O_SERIES && kPacked<LAYOUT>) {
+        // timeseries: the wave steps its lanes together so that it can evaluate the deferred
+        // snapshots of all of them at once
+        using J = SnapJob<typename Real<PREC>::T>;
+        extern __shared__ double dyn_lds[];   // blockDim.x slots
+        J* jobs = reinterpret_cast<J*>(dyn_lds);
+        J* W = jobs + (threadIdx.x & ~63u);
         jobs[threadIdx.x].cnt = 0;
         wave_sync();
         int32_t st = ST_SKIP;
@@ -1119,7 +1121,7 @@ k_track_static(TrackParams P) {
             const unsigned long long pend = __ballot(jobs[threadIdx.x].cnt > 0);
             const unsigned long long live = __ballot(st == 0);
             if (pend != 0ull && (__popcll(pend) >= kSnapFlush || live == 0ull))
-                flush_snaps<LAYOUT, BATCHED>(W, P, snap, L.amb);
+                flush_snaps<PREC, LAYOUT, BATCHED>(W, P, snap, L.amb);
             if (live == 0ull) break;
         }
         if (st > 0) finish<PREC, LAYOUT, OUT, BATCHED>(L, st, P, S.hist);
@@ -1138,7 +1140,7 @@ template <int PREC, int LAYOUT, int OUT, bool BATCHED>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesPersistent<PREC, OUT>)))
 k_track_persistent(TrackParams P) {
     __shared__ BlockShared<OUT == O_SERIES> S;
-    const double* snap = block_setup<OUT == O_SERIES>(S, P);
+    const double* snap = block_setup<PREC, OUT == O_SERIES>(S, P);
     unsigned long long crossings = 0;
     const unsigned long long n = (unsigned long long)P.n;
     const int refill = P.refill;
