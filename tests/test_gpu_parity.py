@@ -162,3 +162,27 @@ def test_schedules_and_shapes_bit_identical(pt):
         out = gpu_track([g], p, **kw)
         for k in ("status", "cell", "ncross", "path_hash", "xi", "eta", "zeta", "t", "out_xyz"):
             assert np.array_equal(out[k], ref[k], equal_nan=True), (kw, k)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_deferred_snapshots_match_immediate(pt, precision):
+    """The static kernel defers snapshots and evaluates them wave-wide; the persistent kernel and
+    the face layout write them at once.  Both forms must give identical snapshots and states in
+    either precision, at every block size (the slots are per thread, the flushes per wave), with
+    snapshots dense enough that lanes meet a second one while their slot is pending."""
+    g = CASES["porosity_field"]
+    rng = np.random.Generator(np.random.PCG64(31))
+    p = C.release(rng, 5000, g.nx, g.ny, g.nz)
+    p.t[:] = rng.choice([0.0, 3.0, 40.0], size=p.n)
+    snaps = np.concatenate([np.linspace(0.0, 20.0, 81), np.logspace(1.5, 3.5, 60)])
+    snaps.sort()
+    kw = dict(snap_times=snaps, t_max=2000.0, precision=precision)
+    ref = gpu_track([g], p, schedule=2, layout=2, **kw)
+    runs = [dict(schedule=1, layout=2), dict(schedule=1, layout=2, block=64), dict(schedule=1, layout=2, block=192),
+            dict(schedule=1, layout=2, sort=2, use_graph=1)]
+    if precision == 0:
+        runs.append(dict(schedule=1, layout=1))
+    for r in runs:
+        out = gpu_track([g], p, **r, **kw)
+        for k in ("status", "cell", "ncross", "path_hash", "xi", "eta", "zeta", "t", "out_xyz", "snap_xyz"):
+            assert np.array_equal(out[k], ref[k], equal_nan=True), (r, k)
