@@ -361,14 +361,24 @@ PT_CR_HD dd expm1_series_accurate(dd r) {
 // (0, 0), |x - r| >= ln2/128 and |2^k T_j q| < 0.502 |2^k T_j - 1| (worst at x - r = ln2/128,
 // r = -ln2/256), so the sum cancels by about a factor of 2 at most: the quick phase adds
 // the low parts plainly (dd_add_fast, error below 2^-100 relative).
+//
+// Quick phase, -1 <= k <= 52: T.h - one is exact (T.h / one = 2^k T_j lies in [1/2, 2^53): for
+// T.h <= 2 one by Sterbenz's lemma, above because one is then a multiple of ulp(T.h) and the
+// difference keeps T.h's exponent or one less), so A = (T.h - one) + T.l needs no error-free sum;
+// its low part may exceed half an ulp of its high part, which dd_add_fast accepts.
 template <bool FAST>
 PT_CR_HD dd expm1_combine(const ExpRed& R, dd q, int s) {
     if (R.k == 0 && R.j == 0) return q;
     const int k = R.k - s;
     const dd T = {ldexp(PT_CR_EXPT(R.j, 0), k), ldexp(PT_CR_EXPT(R.j, 1), k)};
     const double one = ldexp(1.0, -s);
+    if (FAST) {
+        dd A;
+        if (R.k >= -1 && R.k <= 52) A = {T.h - one, T.l};
+        else A = dd_add_d(T, -one);
+        return dd_add_fast(A, dd_mul(T, q));
+    }
     const dd A = dd_add_d(T, -one);
-    if (FAST) return dd_add_fast(A, dd_mul(T, q));
     return dd_add(A, dd_mul(T, q));
 }
 
