@@ -41,6 +41,7 @@ HBM_PEAK_GBS = 8000.0
 # (cell 4, xi/eta/zeta/t 32, status 4, ncross 4, hash 8 = 52 B), written back (52 B) and
 # the final global position (24 B)
 BYTES_PER_CROSSING = {"fp64": 60, "mixed": 32}
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 (FMA) x 2.4 GHz
 BYTES_PER_PARTICLE = 52 + 52 + 24
 
 
@@ -255,10 +256,21 @@ def roofline(res, n, precision, workload, schedule, timeseries=False, batched=Fa
            "traffic": profiled_traffic(workload, precision, schedule),
            "bytes_per_launch": int(bytes_launch), "kernel_ms": round(res["kernel_ms"], 4),
            "kernel": kernel_name(precision, schedule, timeseries, batched)}
-    # the vector-ALU view of the same kernel (issued VALU cycles over available), from counters
+    # the vector-ALU view of the same kernel, from the committed instruction counters: issued VALU
+    # cycles over the available ones, and the FP64 arithmetic rate (add, multiply, transcendental:
+    # one flop per lane slot, FMA two) against the FP64 vector peak
     busy = profile_value("valu", "valu_busy", workload, precision, schedule)
     if busy is not None:
         out["valu_busy"] = busy
+        cnt = [profile_value("valu", "SQ_INSTS_VALU_%s" % k, workload, precision, schedule)
+               for k in ("ADD_F64", "MUL_F64", "FMA_F64", "TRANS_F64")]
+        cross = profile_value("valu", "crossings_per_launch", workload, precision, schedule)
+        if None not in cnt and cross:
+            per_cross = 64.0 * (cnt[0] + cnt[1] + 2.0 * cnt[2] + cnt[3]) / cross
+            tflops = per_cross * res["crossings_per_step"] / (res["kernel_ms"] * 1e-3) / 1e12
+            out["alu"] = {"fp64_flops_per_crossing": round(per_cross, 1), "achieved": round(tflops, 2),
+                          "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4), "valu_busy": busy}
     return out
 
 
