@@ -90,8 +90,10 @@ def test_batched_groups(pt):
             compare(out, r, label="batched sched %d sort %d" % (sched, sort), spacing=(10.0, 10.0, 2.0))
     snaps = np.logspace(-1, 3, 20)
     r = O.track_groups(grids, p, offs, gg, snap_times=snaps, t_max=300.0)
-    out = gpu_track(grids, p, group_offsets=offs, group_grid=gg, snap_times=snaps, t_max=300.0)
-    compare(out, r, label="batched timeseries", spacing=(10.0, 10.0, 2.0))
+    for kw in (dict(), dict(schedule=1, layout=2), dict(schedule=1, layout=2, sort=2, block=128),
+               dict(schedule=2, layout=2)):
+        out = gpu_track(grids, p, group_offsets=offs, group_grid=gg, snap_times=snaps, t_max=300.0, **kw)
+        compare(out, r, label="batched timeseries %s" % kw, spacing=(10.0, 10.0, 2.0))
 
 
 def test_edge_cases(pt):
