@@ -8,7 +8,10 @@
 // so the kernels are data parallel over particles:
 //
 //   * static:     one thread per particle for its whole track (the analogue of
-//                 the paper's static scheduling, Methods "Multiprocessing");
+//                 the paper's static scheduling, Methods "Multiprocessing"); the
+//                 work is ordered by starting cell and dealt to the dies in chunks,
+//                 and in timeseries runs a wave evaluates the snapshots its lanes
+//                 meet together, once enough are pending;
 //   * persistent: resident waves pull particle indices from a device work
 //                 queue; lanes whose particle stopped are refilled at wave level
 //                 (ballot + mbcnt prefix count, one atomic per wave), so slow
