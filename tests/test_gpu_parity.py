@@ -210,3 +210,16 @@ def test_sort_on_grid_beyond_histogram():
     idx = sample_indices(n, 300, seed=42)
     r = O.track(g, p.subset(idx))
     compare(ordered, r, idx=idx, label="large grid", spacing=(2.0, 2.0, 1.0))
+
+
+def test_deferred_snapshots_many_times(pt):
+    """More snapshot times than the block keeps in LDS (read from global memory), in the
+    deferred and the immediate form, against the oracle."""
+    g = CASES["lognormal_wells"]
+    rng = np.random.Generator(np.random.PCG64(33))
+    p = C.release(rng, 700, g.nx, g.ny, g.nz)
+    snaps = np.linspace(0.0, 400.0, 1500)
+    r = O.track(g, p, snap_times=snaps, t_max=400.0)
+    for kw in (dict(schedule=1, layout=2), dict(schedule=2, layout=2), dict(schedule=1, layout=2, block=64)):
+        out = gpu_track([g], p, snap_times=snaps, t_max=400.0, **kw)
+        compare(out, r, label="1500 snapshots %s" % kw, spacing=(10.0, 10.0, 2.0))
