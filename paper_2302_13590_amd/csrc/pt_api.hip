@@ -782,6 +782,8 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
         if (!path_count) {
             P.path_cap = o->path_cap;
             P.path_rec = reinterpret_cast<PathRec*>(o->path_records);
+            // staged record writes need 64-byte aligned segments of the record array
+            P.path_stage = (reinterpret_cast<uintptr_t>(o->path_records) % 64 == 0) ? 1 : 0;
         }
     }
 
@@ -855,7 +857,9 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
         // thread in dynamic LDS
         const bool snap_slots = key.out == O_SERIES && key.sched == S_STATIC && key.layout != L_FACES;
         const size_t slot = key.precision == P64 ? sizeof(SnapJob<double>) : sizeof(SnapJob<float>);
-        seq.push_back({fn, dim3(grid), dim3(block), &P, sizeof P, snap_slots ? slot * (size_t)block : 0});
+        // the pathline record pass stages each lane's records in dynamic LDS
+        const size_t lds = snap_slots ? slot * (size_t)block : (P.path_stage ? sizeof(PathStage) * (size_t)block : 0);
+        seq.push_back({fn, dim3(grid), dim3(block), &P, sizeof P, lds});
         if (path_count) seq.push_back({scan_tiles_kernel(), dim3((unsigned)SC.ntiles), dim3(kScanBlock), &SC, sizeof SC});
     }
     if (path_count) {

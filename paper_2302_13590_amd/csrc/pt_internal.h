@@ -127,16 +127,16 @@ struct TrackParams {
     int32_t steps_per_refill;
     int32_t chunk;
     int32_t pad_chunk;
-    // Processing order: slot s of the work holds particle order[s] (nullptr: s itself).  Slots
-    // are split into kXcd contiguous segments, one per die, so that a die's L2 sees one
-    // spatially coherent part of the particles.
+    // Processing order: slot s of the work holds particle order[s] (nullptr: s itself).  The
+    // static kernel deals the slots to the dies in chunks of kDieChunk blocks; the persistent
+    // queue has one segment per die.
     const int32_t* order;
     // Pathline output (O_PATH kernels).  Count pass (path_count): path_off[p+1] receives the
     // crossings of particle p and no state is written back.  Record pass: the records of p go to
     // slots [path_off[p], path_off[p+1]) that are also below path_cap.
     int64_t* path_off;
     int32_t path_count;
-    int32_t pad_path;
+    int32_t path_stage;   // record pass: records staged per lane in LDS, written in 64-byte segments
     int64_t path_cap;
     PathRec* path_rec;
     // Transient flow (batched kernels): grids[s] is the field of time step s, valid until
@@ -243,5 +243,15 @@ struct SnapJob {
     int32_t start;        // first pair index of the slot in a flush
 };
 static_assert(sizeof(SnapJob<double>) == 72 && sizeof(SnapJob<float>) == 56, "SnapJob layout");
+
+// Staging of one lane's pathline records (record pass): the bytes of the current 64-byte segment
+// of the particle's record stream and the overflow of the last record (12 doubles), and the
+// particle's first record slot.  The kernel takes blockDim.x slots of dynamic LDS.
+struct PathStage {
+    double buf[12];
+    int64_t q0;
+    int64_t pad;
+};
+static_assert(sizeof(PathStage) == 112, "PathStage layout");
 
 }  // namespace pt
