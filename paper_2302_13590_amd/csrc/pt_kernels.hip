@@ -131,34 +131,31 @@ __device__ __forceinline__ double adv64(double u1, double u2, double xi, double 
 
 // Earliest exit over the three axes, FP64, with the same result as evaluating exit_time64 on
 // every axis and keeping the strictly smallest (ties to the lowest axis).  A cheap FP32
-// estimate E of each axis' time is formed first (relative error below 3e-6); when one axis
+// estimate E of each axis' time is formed first (relative error below 1.5e-6); when one axis
 // is ahead of every other by more than 2^-15 relative, only its correctly rounded time is
 // evaluated -- the others cannot be smaller.  Otherwise (near ties, estimates out of the FP32
 // range) every axis is evaluated exactly.
 constexpr double kFilterMargin = 0x1p-15;
 
 // FP32 estimate of (D/u_p) log1p(x)/x, x = A D/u_p, from the hardware reciprocal and base-2
-// logarithm (each within 1 ulp) and, for |x| < 1/8, the series of log1p(x)/x to x^7
-// (truncation below 7e-9).  `unsure` is raised when FP32 cannot bound it.
+// logarithm (within 2 ulp each, relative, over the whole normal range: checked exhaustively on
+// gfx950).  log1p(x)/x is taken as log(u)/(u - 1) with u = fl(1 + x) (Goldberg's form: u - 1 is
+// exact for x > -1/2, and the quotient stays accurate however small x is), one formula for all
+// lanes; for x <= -1/2 the ratio u_e/u_p is formed directly.  Error: ~7 ulp in x, propagated
+// with a factor below 1, ~10 ulp in the quotient, ~6 ulp in D/u_p: below 1.5e-6 relative, a
+// tenth of what the selection margin allows.  `unsure` is raised when FP32 cannot bound it.
 __device__ __forceinline__ float exit_estimate(double D, double up, double A, double ue, bool& unsure) {
     const float upf = (float)up;
     const float rup = __builtin_amdgcn_rcpf(upf);
     const float rf = (float)D * rup;
     const float xf = (float)A * rf;
-    float ph;
-    if (fabsf(xf) < 0.125f) {
-        ph = fmaf(xf, -0.125f, 0.142857143f);
-        ph = fmaf(xf, ph, -0.166666667f);
-        ph = fmaf(xf, ph, 0.2f);
-        ph = fmaf(xf, ph, -0.25f);
-        ph = fmaf(xf, ph, 0.333333333f);
-        ph = fmaf(xf, ph, -0.5f);
-        ph = fmaf(xf, ph, 1.0f);
-    } else {
-        const float q = (xf > -0.5f) ? 1.0f + xf : (float)ue * rup;
-        unsure = unsure || !(q >= 0x1p-100f);
-        ph = (__builtin_amdgcn_logf(q) * 0.693147181f) * __builtin_amdgcn_rcpf(xf);
-    }
+    const float u = 1.0f + xf;
+    const bool ratio = !(xf > -0.5f);
+    const float q = ratio ? (float)ue * rup : u;   // u_e/u_p
+    const float den = ratio ? xf : u - 1.0f;
+    unsure = unsure || !(q >= 0x1p-100f);
+    const float ph = (u == 1.0f) ? 1.0f   // |x| < 2^-24: log1p(x)/x = 1 - x/2 + ...
+                                 : (__builtin_amdgcn_logf(q) * 0.693147181f) * __builtin_amdgcn_rcpf(den);
     const float E = rf * ph;
     unsure = unsure || !(fabsf(upf) >= 0x1p-100f && fabsf(upf) <= 0x1p100f) || !__builtin_isfinite(E);
     return E;
@@ -232,33 +229,14 @@ __device__ __forceinline__ void select_exit64(const double (&u1)[3], const doubl
 
 // ---------------------------------------------------------------------------------------------
 // One axis, mixed precision: FP32 velocities, local coordinate and in-cell arithmetic, with
-// the hardware reciprocal, base-2 logarithm and exponential (1 ulp each) and short series
-// near zero; FP64 for time and for the near-zero-gradient branch (|x| < 2^-10 or
-// |A tau| < 2^-10), where the series are evaluated in double.
+// the hardware reciprocal, base-2 logarithm and exponential (within 2 ulp each, relative);
+// FP64 for time and for the near-zero-gradient branch (|x| < 2^-10 or |A tau| < 2^-10), where
+// short series are evaluated in double.  Beyond it one branch-free formula serves every lane:
+// log1p(x)/x = log(u)/(u - 1) with u = fl(1 + x) (Goldberg), and expm1(y)/y = (v - 1)/log(v)
+// with v = fl(e^y) (Kahan: the logarithm of the rounded exponential compensates its rounding).
 constexpr float kNearZero = 0x1p-10f;
 constexpr float kLn2f = 0.693147181f;
 constexpr float kLog2ef = 1.44269504f;
-
-// log1p(x)/x for |x| < 1/8, series to x^7 (truncation below 7e-9)
-__device__ __forceinline__ float log1p_over_x_series(float x) {
-    float p = fmaf(x, -0.125f, 0.142857143f);
-    p = fmaf(x, p, -0.166666667f);
-    p = fmaf(x, p, 0.2f);
-    p = fmaf(x, p, -0.25f);
-    p = fmaf(x, p, 0.333333333f);
-    p = fmaf(x, p, -0.5f);
-    return fmaf(x, p, 1.0f);
-}
-
-// expm1(y)/y for |y| < 1/8, series to y^6 (truncation below 3e-11)
-__device__ __forceinline__ float expm1_over_y_series(float y) {
-    float p = fmaf(y, 1.98412698e-4f, 1.38888889e-3f);
-    p = fmaf(y, p, 8.33333333e-3f);
-    p = fmaf(y, p, 4.16666667e-2f);
-    p = fmaf(y, p, 0.166666667f);
-    p = fmaf(y, p, 0.5f);
-    return fmaf(y, p, 1.0f);
-}
 
 __device__ __forceinline__ double exit_time_mix(float u1, float u2, float xi, float& xe, unsigned& amb) {
     (void)amb;
@@ -287,13 +265,13 @@ __device__ __forceinline__ double exit_time_mix(float u1, float u2, float xi, fl
         const double ph = 1.0 + xd * (-0.5 + xd * (1.0 / 3.0 + xd * (-0.25 + 0.2 * xd)));
         return rd * ph;
     }
-    float ph;
-    if (fabsf(x) < 0.125f) {
-        ph = log1p_over_x_series(x);
-    } else {
-        const float q = (x > -0.5f) ? 1.0f + x : ue * rup;   // q = u_e/u_p
-        ph = (__builtin_amdgcn_logf(q) * kLn2f) * __builtin_amdgcn_rcpf(x);
-    }
+    // u - 1 is exact for x > -1/2 and not zero here; for x <= -1/2 the ratio q = u_e/u_p is formed
+    // directly and divided by x
+    const float u = 1.0f + x;
+    const bool ratio = !(x > -0.5f);
+    const float q = ratio ? ue * rup : u;
+    const float den = ratio ? x : u - 1.0f;
+    const float ph = (__builtin_amdgcn_logf(q) * kLn2f) * __builtin_amdgcn_rcpf(den);
     float dt = r * ph;
     if (dt < 0.0f) dt = 0.0f;
     return (double)dt;
@@ -313,9 +291,10 @@ __device__ __forceinline__ float adv_mix(float u1, float u2, float xi, double ta
         const double psi = 1.0 + yd * (0.5 + yd * (1.0 / 6.0 + yd * (1.0 / 24.0 + yd * (1.0 / 120.0))));
         xn = (float)((double)xi + ((double)up * tau) * psi);
     } else {
-        float ps;
-        if (fabsf(y) < 0.125f) ps = expm1_over_y_series(y);
-        else ps = (__builtin_amdgcn_exp2f(y * kLog2ef) - 1.0f) * __builtin_amdgcn_rcpf(y);
+        // v - 1 is exact for |y| < 1/8 (Sterbenz) and not zero here; beyond, (v - 1)/y
+        const float v = __builtin_amdgcn_exp2f(y * kLog2ef);
+        const float den = (fabsf(y) < 0.125f) ? __builtin_amdgcn_logf(v) * kLn2f : y;
+        const float ps = (v - 1.0f) * __builtin_amdgcn_rcpf(den);
         xn = xi + (up * tf) * ps;
     }
     xn = (xn < 0.0f) ? 0.0f : xn;
