@@ -242,27 +242,22 @@ __device__ __forceinline__ double exit_time_mix(float u1, float u2, float xi, fl
     (void)amb;
     const float A = u2 - u1;
     const float up = u1 + A * xi;
-    float ue;
-    if (up > 0.0f) {
-        xe = 1.0f;
-        ue = u2;
-        if (!(ue > 0.0f)) return dinf();
-    } else if (up < 0.0f) {
-        xe = 0.0f;
-        ue = u1;
-        if (!(ue < 0.0f)) return dinf();
-    } else {
-        return dinf();
-    }
+    const bool pos = up > 0.0f;
+    xe = pos ? 1.0f : 0.0f;
+    const float ue = pos ? u2 : u1;
+    if (!((pos && ue > 0.0f) | (up < 0.0f && ue < 0.0f))) return dinf();
     const float D = xe - xi;
     const float rup = __builtin_amdgcn_rcpf(up);
     const float r = D * rup;
     const float x = A * r;
     if (fabsf(x) < kNearZero) {
+        // D/u_p from the FP32 quotient and its residual D - u_p r (exact in FP64: u_p r is a
+        // 48-bit product), corrected once with the FP32 reciprocal: relative error ~2^-46.
         // log1p(x)/x = 1 - x/2 + x^2/3 - x^3/4 + x^4/5 - ..., truncation below 2^-52 here
-        const double rd = (double)D / (double)up;
+        const double rd0 = (double)r;
+        const double rd = fma((double)rup, fma(-(double)up, rd0, (double)D), rd0);
         const double xd = (double)A * rd;
-        const double ph = 1.0 + xd * (-0.5 + xd * (1.0 / 3.0 + xd * (-0.25 + 0.2 * xd)));
+        const double ph = fma(xd, fma(xd, fma(xd, fma(xd, 0.2, -0.25), 1.0 / 3.0), -0.5), 1.0);
         return rd * ph;
     }
     // u - 1 is exact for x > -1/2 and not zero here; for x <= -1/2 the ratio q = u_e/u_p is formed
@@ -288,8 +283,8 @@ __device__ __forceinline__ float adv_mix(float u1, float u2, float xi, double ta
     if (fabsf(y) < kNearZero) {
         // expm1(y)/y = 1 + y/2 + y^2/6 + y^3/24 + y^4/120 + ..., truncation below 2^-59 here
         const double yd = (double)A * tau;
-        const double psi = 1.0 + yd * (0.5 + yd * (1.0 / 6.0 + yd * (1.0 / 24.0 + yd * (1.0 / 120.0))));
-        xn = (float)((double)xi + ((double)up * tau) * psi);
+        const double psi = fma(yd, fma(yd, fma(yd, fma(yd, 1.0 / 120.0, 1.0 / 24.0), 1.0 / 6.0), 0.5), 1.0);
+        xn = (float)fma((double)up * tau, psi, (double)xi);
     } else {
         // v - 1 is exact for |y| < 1/8 (Sterbenz) and not zero here; beyond, (v - 1)/y
         const float v = __builtin_amdgcn_exp2f(y * kLog2ef);
