@@ -389,7 +389,7 @@ int pt_load_grid(const pt_grid_desc* d, void* hip_stream, pt_grid** out) {
     gd.dx = d->dx; gd.dy = d->dy; gd.dz = d->dz;
     gd.x0 = d->x0; gd.y0 = d->y0; gd.z0 = d->z0;
     gd.V = (d->dx * d->dy) * d->dz;
-    gd.nx = d->nx; gd.ny = d->ny; gd.nz = d->nz; gd.pad = 0;
+    gd.nx = d->nx; gd.ny = d->ny; gd.nz = d->nz; gd.plane = d->nx * d->ny;
     BuildParams B;
     B.g = gd;
     B.rec64 = static_cast<CellRec64*>(r64);
@@ -533,6 +533,7 @@ int pt_load_quad_grid(const pt_quad_desc* d, void* hip_stream, pt_grid** out) {
     gd.nx = d->ncell;
     gd.ny = 1;
     gd.nz = 1;
+    gd.plane = 1;
     gd.qbox = static_cast<const QuadBox*>(box);
     gd.sub_nb = static_cast<const int32_t*>(nb);
     gd.sub_rect = static_cast<const double4*>(sr);

@@ -69,7 +69,7 @@ struct GridDev {
     double por_scalar;
     double dx, dy, dz, x0, y0, z0;
     double V;               // (dx*dy)*dz
-    int32_t nx, ny, nz, pad;
+    int32_t nx, ny, nz, plane;   // plane = nx ny (structured), 1 (quadtree)
     // quadtree grids (nx = number of cells, ny = nz = 1; rec64 points at QuadRec records)
     const QuadBox* qbox;
     const int32_t* sub_nb;

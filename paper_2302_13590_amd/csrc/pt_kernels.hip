@@ -1032,19 +1032,13 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
         if (!(nfl & CF_ACTIVE)) return ST_INACTIVE_NB;
         nfl_sink = (nfl & CF_SINK) ? 1 : 0;
     }
+    // cell id stride of the axis, selected from uniform values (no per-lane multiply)
+    const int32_t stride = (axis == 0) ? 1 : ((axis == 1) ? G.nx : G.plane);
+    L.c += hi ? stride : -stride;
     if constexpr (kTrackIJK<LAYOUT, OUT>) {
-        if (axis == 0) {
-            L.i += step;
-            L.c += step;
-        } else if (axis == 1) {
-            L.j += step;
-            L.c += step * G.nx;
-        } else {
-            L.k += step;
-            L.c += step * G.nx * G.ny;
-        }
-    } else {
-        L.c += step * ((axis == 0) ? 1 : ((axis == 1) ? G.nx : G.nx * G.ny));
+        L.i += (axis == 0) ? step : 0;
+        L.j += (axis == 1) ? step : 0;
+        L.k += (axis == 2) ? step : 0;
     }
     L.x[0] = (axis == 0) ? (R)1 - xe : L.x[0];
     L.x[1] = (axis == 1) ? (R)1 - xe : L.x[1];
