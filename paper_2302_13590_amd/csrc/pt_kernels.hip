@@ -387,11 +387,18 @@ __device__ __forceinline__ void load_rec(const GridDev& G, int32_t c, double sig
         const float4* r = reinterpret_cast<const float4*>(G.rec32 + c);
         const float4 a = r[0];
         const float4 b = r[1];
-        const float fs = (float)sign;
         fl = __float_as_int(b.z);
-        u1[0] = fs * a.x; u2[0] = fs * a.y;
-        u1[1] = fs * a.z; u2[1] = fs * a.w;
-        u1[2] = fs * b.x; u2[2] = fs * b.y;
+        u1[0] = a.x; u2[0] = a.y;
+        u1[1] = a.z; u2[1] = a.w;
+        u1[2] = b.x; u2[2] = b.y;
+        if (sign != 1.0) {   // backward tracking (uniform across the launch)
+            const float fs = (float)sign;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                u1[q] = fs * u1[q];
+                u2[q] = fs * u2[q];
+            }
+        }
     }
 }
 
