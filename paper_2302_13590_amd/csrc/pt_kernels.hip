@@ -241,7 +241,7 @@ constexpr float kLog2ef = 1.44269504f;
 __device__ __forceinline__ double exit_time_mix(float u1, float u2, float xi, float& xe, unsigned& amb) {
     (void)amb;
     const float A = u2 - u1;
-    const float up = u1 + A * xi;
+    const float up = fmaf(A, xi, u1);
     const bool pos = up > 0.0f;
     xe = pos ? 1.0f : 0.0f;
     const float ue = pos ? u2 : u1;
@@ -275,7 +275,7 @@ __device__ __forceinline__ double exit_time_mix(float u1, float u2, float xi, fl
 __device__ __forceinline__ float adv_mix(float u1, float u2, float xi, double tau, unsigned& amb) {
     (void)amb;
     const float A = u2 - u1;
-    const float up = u1 + A * xi;
+    const float up = fmaf(A, xi, u1);
     if (up == 0.0f) return xi;
     const float tf = (float)tau;
     const float y = A * tf;
@@ -290,7 +290,7 @@ __device__ __forceinline__ float adv_mix(float u1, float u2, float xi, double ta
         const float v = __builtin_amdgcn_exp2f(y * kLog2ef);
         const float den = (fabsf(y) < 0.125f) ? __builtin_amdgcn_logf(v) * kLn2f : y;
         const float ps = (v - 1.0f) * __builtin_amdgcn_rcpf(den);
-        xn = xi + (up * tf) * ps;
+        xn = fmaf(up * tf, ps, xi);
     }
     xn = (xn < 0.0f) ? 0.0f : xn;
     xn = (xn > 1.0f) ? 1.0f : xn;
