@@ -272,10 +272,7 @@ __device__ __forceinline__ double exit_time_mix(float u1, float u2, float xi, fl
     return (double)dt;
 }
 
-__device__ __forceinline__ float adv_mix(float u1, float u2, float xi, double tau, unsigned& amb) {
-    (void)amb;
-    const float A = u2 - u1;
-    const float up = fmaf(A, xi, u1);
+__device__ __forceinline__ float adv_mix_au(float A, float up, float xi, double tau) {
     if (up == 0.0f) return xi;
     const float tf = (float)tau;
     const float y = A * tf;
@@ -295,6 +292,12 @@ __device__ __forceinline__ float adv_mix(float u1, float u2, float xi, double ta
     xn = (xn < 0.0f) ? 0.0f : xn;
     xn = (xn > 1.0f) ? 1.0f : xn;
     return xn;
+}
+
+__device__ __forceinline__ float adv_mix(float u1, float u2, float xi, double tau, unsigned& amb) {
+    (void)amb;
+    const float A = u2 - u1;
+    return adv_mix_au(A, fmaf(A, xi, u1), xi, tau);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -985,8 +988,12 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
             na = adv64_au(Ax, ux, xa, dt, L.amb);
             nb = adv64_au(Ay, uy, xb, dt, L.amb);
         } else {
-            na = adv<PREC>(v1a, v2a, xa, dt, L.amb);
-            nb = adv<PREC>(v1b, v2b, xb, dt, L.amb);
+            // the gradient and particle velocity as the exit times formed them
+            const float A0 = u2[0] - u1[0], A1 = u2[1] - u1[1], A2 = u2[2] - u1[2];
+            const float p0 = fmaf(A0, L.x[0], u1[0]), p1 = fmaf(A1, L.x[1], u1[1]), p2 = fmaf(A2, L.x[2], u1[2]);
+            (void)v1a, (void)v2a, (void)v1b, (void)v2b;
+            na = adv_mix_au((a1 == 0) ? A0 : A1, (a1 == 0) ? p0 : p1, xa, dt);
+            nb = adv_mix_au((a2 == 1) ? A1 : A2, (a2 == 1) ? p1 : p2, xb, dt);
         }
         L.x[0] = (axis == 0) ? xe : na;
         L.x[1] = (axis == 1) ? xe : ((a1 == 1) ? na : nb);
