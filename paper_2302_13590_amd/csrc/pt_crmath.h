@@ -105,10 +105,13 @@ PT_CR_HD dd dd_add(dd x, dd y) {
     return fast_two_sum(v.h, t.l + v.l);
 }
 
-// x + y when no cancellation beyond a factor of a few can occur (the two high parts are
-// summed exactly, the low parts plainly): about half the operations of dd_add.
+// x + y when |x.h| >= |y.h| (or x.h == 0) and no cancellation beyond a factor of a few can occur:
+// the two high parts are summed exactly by the ordered error-free sum, the low parts plainly.
+// Every caller meets the ordering: in log_sum |ln c_j| >= ln(256/255) > |log1p(r)| (|r| < 2^-8.4)
+// or c_j = 1, and |k ln 2| >= ln 2 > |ln m| (m in [sqrt(1/2), sqrt(2)]) or k = 0; in expm1_combine
+// |2^k T_j q| < 0.502 |2^k T_j - 1|.
 PT_CR_HD dd dd_add_fast(dd x, dd y) {
-    const dd s = two_sum(x.h, y.h);
+    const dd s = fast_two_sum(x.h, y.h);
     return fast_two_sum(s.h, s.l + (x.l + y.l));
 }
 
