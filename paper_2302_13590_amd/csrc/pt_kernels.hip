@@ -134,7 +134,8 @@ __device__ __forceinline__ double adv64(double u1, double u2, double xi, double 
 // estimate E of each axis' time is formed first (relative error below 1.5e-6); when one axis
 // is ahead of every other by more than 2^-15 relative, only its correctly rounded time is
 // evaluated -- the others cannot be smaller.  Otherwise (near ties, estimates out of the FP32
-// range) every axis is evaluated exactly.
+// range) every axis is evaluated exactly.  The estimates and the limit stay in FP32: the limit's
+// own rounding (2^-24) is far inside the margin left by two estimates' errors.
 constexpr double kFilterMargin = 0x1p-15;
 
 // FP32 estimate of (D/u_p) log1p(x)/x, x = A D/u_p, from the hardware reciprocal and base-2
@@ -165,7 +166,7 @@ __device__ __forceinline__ void select_exit64(const double (&u1)[3], const doubl
                                               const double (&xi)[3], double& dt, int32_t& axis,
                                               double& xe, unsigned& amb, double (&Ao)[3],
                                               double (&upo)[3]) {
-    double E[3];
+    float E[3];
     bool unsure = false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -188,14 +189,14 @@ __device__ __forceinline__ void select_exit64(const double (&u1)[3], const doubl
             ue = 0.0;
             feasible = false;
         }
-        double est = dinf();
-        if (feasible) est = (double)exit_estimate(e - xi[a], up, A, ue, unsure);
+        float est = __builtin_inff();
+        if (feasible) est = exit_estimate(e - xi[a], up, A, ue, unsure);
         E[a] = est;
     }
     // candidate axis, then its inputs by selects (constant indices only: the arrays stay in
     // registers)
     int32_t w = -1;
-    double Ew = dinf();
+    float Ew = __builtin_inff();
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const bool lt = E[a] < Ew;
@@ -205,7 +206,7 @@ __device__ __forceinline__ void select_exit64(const double (&u1)[3], const doubl
     const double w1 = (w == 0) ? u1[0] : ((w == 1) ? u1[1] : u1[2]);
     const double w2 = (w == 0) ? u2[0] : ((w == 1) ? u2[1] : u2[2]);
     const double wx = (w == 0) ? xi[0] : ((w == 1) ? xi[1] : xi[2]);
-    const double lim = Ew * (1.0 + kFilterMargin);
+    const float lim = Ew * (1.0f + (float)kFilterMargin);   // exact: 1 + 2^-15 is a float
 #pragma unroll
     for (int a = 0; a < 3; ++a) unsure = unsure || (a != w && E[a] <= lim);
     if (!unsure) {

@@ -91,7 +91,8 @@ def test_exit_estimate_within_claimed_bound():
         assert np.all(np.isfinite(rel))
         worst = max(worst, float(rel.max()))
     assert worst < BOUND, worst
-    assert 2 * BOUND < MARGIN          # two estimates' errors stay inside the selection margin
+    # two estimates' errors and the FP32 rounding of the limit E_w (1 + 2^-15) stay inside the margin
+    assert 2 * BOUND + 2.0 ** -24 < MARGIN
 
 
 def test_exit_estimate_regimes_separately():
