@@ -3,24 +3,31 @@
 
 One step = one pass of the whole tracking path over one batch: restore the
 released particle state (device-to-device copy), track every particle to its
-stopping condition through the C ABI (pt_track: counter reset + tracking
-kernel), and read the run summary (pt_results).  Grids and particles are
-resident in HBM before the timed region starts.  The K timed steps are
+stopping condition through the C ABI (pt_track: counter reset, ordering sort,
+tracking kernel), and read the run summary (pt_results).  Grids and particles
+are resident in HBM before the timed region starts.  The K timed steps are
 enqueued back to back on one stream and their summaries read afterwards, so
 the timed region holds the device work of K steps and no host wait between
 them.
 
-Default workload (C2): 100x100x10 cells of 10x10x2 m, lognormal K with
-geometric mean 10 m/d, sigma^2 = 1, correlation length 5 cells, heads 10/0 m
-west/east, porosity 0.3; 1e6 particles released uniformly in the 10 western
-columns; endpoint mode, FP64, packed cell records, hipGraph launch, with the
-autotuned launch of this device and workload (paper_2302_13590_amd/tuning.json:
-schedule, block size, processing order).  The same steps are also timed for the
-static and persistent kernels, the mixed-precision kernel and the pathline mode
-(count pass + record pass, one record per crossing), and the CPU oracle is timed
-on the host cores.
+Default workload (C4, the batched form of the metric): 16 realisations of a
+100x100x10 grid of 10x10x2 m cells, lognormal K with geometric mean 10 m/d,
+sigma^2 drawn from U[0.5, 4], correlation length 5 cells, heads 10/0 m
+west/east, porosity 0.3; 64 particle groups of log-uniform sizes in [1e3, 2e6]
+(1.77e7 particles) released in the 10 western columns, group g on realisation
+g mod 16; endpoint mode, FP64, packed cell records, one hipGraph launch over
+every group, with the autotuned launch of this device and workload
+(paper_2302_13590_amd/tuning.json: schedule, block size, processing order).
 
-Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+Also timed in the same run: the other FP64 kernel and the mixed-precision
+kernel on C4 (with its path and travel-time accuracy against the FP64 run and
+against the oracle); C2 (FP64, mixed, pathline mode), C3 (FP64, mixed), C5
+(timeseries, FP64 and mixed with the snapshot position error), C6 (transient
+flow) and C7 (quadtree).  The CPU oracle is timed on the host cores on a
+sample of C4, and the FP64 run is compared bitwise with the oracle on that
+sample.
+
+Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W] [--workload W]
 """
 from __future__ import annotations
 
@@ -50,6 +57,14 @@ def log(msg):
 
 
 def host_cpu_model():
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
@@ -279,46 +294,44 @@ def tuned_params(workload, precision, mode):
     return autotune.lookup(autotune.key(autotune.device_name(), workload, precision, mode))
 
 
-def final_state(case):
-    """Host copy of the final state of the last step run on `case` (status, time, path)."""
-    d = case.work.to_numpy()
-    return {k: d[k] for k in ("status", "t", "ncross", "path_hash")}
+def oracle_sample_indices(n, m):
+    """Every ceil(n/m)-th particle: a bounded sample that spans every group of a batched run."""
+    stride = max(1, -(-n // m))
+    return np.arange(0, n, stride)
 
 
-def path_accuracy(mix, ref, t0):
-    """Cell-path agreement (same path hash and crossing count) of a mixed-precision result with an
-    FP64 one, and the relative error of the travel time of the particles that both brought to a
-    boundary.  mix, ref: final states of the same particles; t0: their release times."""
-    same = (mix["path_hash"] == ref["path_hash"]) & (mix["ncross"] == ref["ncross"])
-    done = (ref["status"] == 1) & (mix["status"] == 1)
-    tt = ref["t"][done] - t0[done]
-    pos = tt > 0
-    rel = np.abs((mix["t"][done] - t0[done])[pos] - tt[pos]) / tt[pos]
-    q = np.quantile(rel, [0.5, 0.99, 1.0]) if rel.size else [float("nan")] * 3
-    return {"particles": int(same.size), "path_agreement": round(float(same.mean()), 6),
-            "travel_time_rel_err": {"p50": float(q[0]), "p99": float(q[1]), "max": float(q[2]),
-                                    "particles": int(rel.size)}}
-
-
-def cpu_baseline(w, n_threads):
-    """The oracle (plain FP64 CPU tracker) on the host cores, on a bounded sample."""
+def oracle_on_sample(w, idx, threads):
+    """The oracle (plain FP64 CPU tracker) on the particles idx of workload w, per group for
+    batched runs; returns (result, seconds)."""
     from oracle import oracle as O
-    p = w.particles
-    res = {}
-    # all host cores, dynamic scheduling of the particle loop (the paper's best protocol)
-    m = min(p.n, 500_000)
-    sub = p.subset(slice(0, m))
+    sub = w.particles.subset(idx)
     t0 = time.perf_counter()
-    r = O.track(w.grids[0], sub, t_max=w.t_max, threads=n_threads)
-    dt = time.perf_counter() - t0
-    res["all_cores"] = dict(value=float(r.ncross.astype(np.int64).sum()) / dt, seconds=dt, particles=m)
-    res["sample_result"] = r
-    m1 = min(p.n, 50_000)
-    t0 = time.perf_counter()
-    r1 = O.track(w.grids[0], p.subset(slice(0, m1)), t_max=w.t_max, threads=1)
-    dt1 = time.perf_counter() - t0
-    res["one_core"] = dict(value=float(r1.ncross.astype(np.int64).sum()) / dt1, seconds=dt1, particles=m1)
-    return res
+    if w.group_offsets is None:
+        r = O.track(w.grids[0], sub, t_max=w.t_max, snap_times=w.snap_times, threads=threads)
+    else:
+        offs = np.searchsorted(idx, w.group_offsets).astype(np.int64)
+        r = O.track_groups(w.grids, sub, offs, w.group_grid, t_max=w.t_max, threads=threads)
+    return r, time.perf_counter() - t0
+
+
+def cpu_share():
+    """Host threads this process may use: the affinity mask, capped by OMP_NUM_THREADS when set
+    (the CPU share of one GPU on a shared host)."""
+    cores = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return (min(cores, int(env)) if env.isdigit() and int(env) > 0 else cores), cores
+
+
+def fp64_parity(state, r, idx):
+    """Bitwise comparison of the FP64 GPU final state with the oracle on the sample."""
+    eq = np.ones(idx.size, dtype=bool)
+    for k in ("cell", "status", "ncross", "path_hash", "xi", "eta", "zeta", "t"):
+        a, b = state[k][idx], getattr(r, k)
+        eq &= (a == b) | (np.isnan(a) & np.isnan(b)) if a.dtype.kind == "f" else (a == b)
+    a, b = state["out_xyz"][idx], r.out_xyz
+    eq &= ((a == b) | (np.isnan(a) & np.isnan(b))).all(axis=1)
+    return {"particles": int(idx.size), "bitwise_equal": int(eq.sum()),
+            "reference": "the FP64 oracle (plain CPU tracker) on the CPU-baseline sample"}
 
 
 # launch parameters of the scheduling study (the tuned C2/C3 shapes of each kernel)
@@ -369,15 +382,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="C2", choices=sorted(DESCR))
+    ap.add_argument("--workload", default="C4", choices=sorted(DESCR))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--schedule", default="auto", choices=["auto", "persistent", "static"],
                     help="auto: the autotuned launch for this workload (tuning.json)")
     ap.add_argument("--only", action="store_true",
                     help="time only the primary variant (no other variants, no CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-pathline", action="store_true",
-                    help="skip the pathline variant (its records take 40 B per crossing of device memory)")
+    ap.add_argument("--no-extra-workloads", action="store_true",
+                    help="time only the chosen workload's variants, not the other workloads")
+    ap.add_argument("--cpu-sample", type=int, default=500_000,
+                    help="particles of the oracle's all-threads sample (the one-thread leg takes a tenth)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain elementwise copy of this many bytes (HBM-counter calibration)")
     ap.add_argument("--study", choices=["scheduling"],
@@ -396,6 +411,7 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    from paper_2302_13590_amd import accuracy as ACC
     from paper_2302_13590_amd import pt
     pt.load_library()
     if args.study == "scheduling":
@@ -410,16 +426,8 @@ def main():
         torch.add(src, 0.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    log("building workload %s" % args.workload)
-    t0 = time.perf_counter()
-    w = workload(args.workload)
-    n = w.particles.n
-    mode = "timeseries" if w.snap_times is not None else "endpoint"
-    batched = len(w.grids) > 1
-    log("inputs ready in %.1fs: %d particles, %d grid(s)" % (time.perf_counter() - t0, n, len(w.grids)))
-    case = Case(w)
 
-    def launch(precision, schedule, wname=args.workload, wmode=mode):
+    def launch(precision, schedule, wname, wmode):
         """Launch parameters: the autotuned ones when they use this schedule, else defaults."""
         tuned = tuned_params(wname, precision, wmode) or {}
         sched_id = 1 if schedule == "static" else 2
@@ -431,57 +439,94 @@ def main():
             return tuned, schedule
         return dict(schedule=sched_id), schedule
 
-    params, sched = launch(args.precision, args.schedule)
-    primary = case.time(case.opts(args.precision, sched, **params), args.steps, args.warmup)
-    ref_state = final_state(case) if args.precision == "fp64" else None
-    mix_state = None
-    t_release = w.particles.t
-    log("primary %s/%s %s: %.4g crossings/s, %.3f ms/step, kernel %.3f ms" % (
-        args.precision, sched, params, primary["value"], primary["ms_per_step"], primary["kernel_ms"]))
-    variants = {}
-    if not args.only:
-        for prec, sc in (("fp64", "static"), ("fp64", "persistent"), ("mixed", "auto")):
-            p2, s2 = launch(prec, sc)
-            if (prec, s2) == (args.precision, sched):
+    def state_of(case):
+        d = case.work.to_numpy()
+        d["out_xyz"] = case.out_xyz.cpu().numpy()
+        return d
+
+    def bench_workload(wname, precision, schedule, extra_variants, acc_oracle=None):
+        """Time one workload: the primary kernel, then the variants; returns (primary, variants,
+        FP64 final state, inputs)."""
+        t0 = time.perf_counter()
+        w = workload(wname)
+        n = w.particles.n
+        mode = "timeseries" if w.snap_times is not None else "endpoint"
+        batched = len(w.grids) > 1 and w.tstep_end is None
+        log("%s ready in %.1fs: %d particles, %d grid(s)" % (wname, time.perf_counter() - t0, n, len(w.grids)))
+        case = Case(w)
+        params, sched = launch(precision, schedule, wname, mode)
+        primary = case.time(case.opts(precision, sched, **params), args.steps, args.warmup)
+        primary.update(params=params, schedule=sched, mode=mode, batched=batched, n=n, workload=wname)
+        log("%s %s/%s %s: %.4g crossings/s, %.3f ms/step, kernel %.3f ms" % (
+            wname, precision, sched, params, primary["value"], primary["ms_per_step"], primary["kernel_ms"]))
+        ref_state = state_of(case) if precision == "fp64" else None
+        ref_snap = case.snap.clone() if (case.snap is not None and precision == "fp64") else None
+        variants = {}
+        for prec, sc in extra_variants:
+            p2, s2 = launch(prec, sc, wname, mode)
+            if (prec, s2) == (precision, sched):
                 continue
             r = case.time(case.opts(prec, s2, **p2), args.steps, args.warmup)
-            variants["%s_%s" % (prec, s2)] = dict(
-                value=r["value"], ms_per_step=round(r["ms_per_step"], 4),
-                kernel_ms=round(r["kernel_ms"], 4), crossings_per_step=r["crossings_per_step"],
-                launch=p2, roofline_frac=roofline(r, n, prec, args.workload, s2, mode == "timeseries",
-                                                  batched)["frac"])
+            tag = "%s_%s_%s" % (wname, prec, s2)
+            v = dict(value=r["value"], ms_per_step=round(r["ms_per_step"], 4),
+                     kernel_ms=round(r["kernel_ms"], 4), crossings_per_step=r["crossings_per_step"],
+                     launch=p2, roofline_frac=roofline(r, n, prec, wname, s2, mode == "timeseries", batched)["frac"])
             if prec == "mixed" and ref_state is not None:
-                mix_state = final_state(case)
-                acc = path_accuracy(mix_state, ref_state, t_release)
-                acc["reference"] = "the FP64 run above (bitwise identical to the FP64 oracle in the parity tests)"
-                variants["%s_%s" % (prec, s2)]["accuracy"] = acc
-                log("mixed accuracy: path agreement %.4f, travel time rel. err. p50 %.2e p99 %.2e" % (
-                    acc["path_agreement"], acc["travel_time_rel_err"]["p50"], acc["travel_time_rel_err"]["p99"]))
-            log("variant %s/%s: %.4g crossings/s" % (prec, s2, r["value"]))
-        if mode == "endpoint" and not args.no_pathline:
-            r = case.time_pathline(args.precision, sched, args.steps, args.warmup, **params)
-            variants["%s_pathline" % args.precision] = dict(
+                mix = state_of(case)
+                acc = ACC.path_agreement(mix, ref_state, w.particles.t)
+                acc["reference"] = "the FP64 run of every particle (bitwise identical to the FP64 oracle in the parity tests)"
+                v["accuracy"] = acc
+                if ref_snap is not None:
+                    tr = ACC.trajectory_error(case.snap, ref_snap)
+                    tr["reference"] = "the FP64 run's snapshots of every particle"
+                    v["trajectory_error"] = tr
+                if acc_oracle is not None:
+                    idx, ro = acc_oracle(w)
+                    sub = {k: mix[k][idx] for k in ("status", "t", "ncross", "path_hash")}
+                    ao = ACC.path_agreement(sub, {k: getattr(ro, k) for k in sub}, w.particles.t[idx])
+                    ao["reference"] = "the FP64 oracle on %d sampled particles" % idx.size
+                    v["accuracy_vs_oracle"] = ao
+                    if ro.snap_xyz is not None:
+                        to = ACC.trajectory_error(case.snap[torch.from_numpy(idx).cuda()].cpu().numpy(), ro.snap_xyz)
+                        to["reference"] = "the FP64 oracle's snapshots of %d sampled particles" % idx.size
+                        v["trajectory_error_vs_oracle"] = to
+                log("%s mixed accuracy: path agreement %.4f, travel time rel. err. p50 %.2e p99 %.2e" % (
+                    wname, acc["path_agreement"], acc["travel_time_rel_err"]["p50"], acc["travel_time_rel_err"]["p99"]))
+            variants[tag] = v
+            log("variant %s: %.4g crossings/s, kernel %.3f ms" % (tag, r["value"], r["kernel_ms"]))
+        if mode == "endpoint" and wname == "C2":
+            r = case.time_pathline("fp64", sched, args.steps, args.warmup, **params)
+            variants["C2_fp64_pathline"] = dict(
                 value=r["value"], ms_per_step=round(r["ms_per_step"], 4), count_ms=round(r["count_ms"], 4),
                 record_ms=round(r["record_ms"], 4), records_per_step=r["records_per_step"],
                 record_bytes_per_step=r["record_bytes"],
                 launch=params, note="count pass + record pass per step (one record of 40 B per crossing)")
             log("variant pathline: %.4g crossings/s, count %.3f ms + record %.3f ms" % (
                 r["value"], r["count_ms"], r["record_ms"]))
-    case.release()
-    if not args.only and args.workload == "C2":
-        # the transient-flow and quadtree workloads, FP64, their tuned launches
-        for wname, tag in (("C6", "fp64_transient_C6"), ("C7", "fp64_quadtree_C7")):
-            t0 = time.perf_counter()
-            c2 = Case(workload(wname))
-            log("%s ready in %.1fs" % (wname, time.perf_counter() - t0))
-            p2, s2 = launch("fp64", "auto", wname, "endpoint")
-            r = c2.time(c2.opts("fp64", s2, **p2), args.steps, args.warmup)
-            c2.release()
-            variants[tag] = dict(value=r["value"], ms_per_step=round(r["ms_per_step"], 4),
-                                 kernel_ms=round(r["kernel_ms"], 4), crossings_per_step=r["crossings_per_step"],
-                                 launch=p2, workload=DESCR[wname])
-            log("variant %s: %.4g crossings/s, kernel %.3f ms" % (tag, r["value"], r["kernel_ms"]))
+        case.release()
+        del case
+        torch.cuda.empty_cache()
+        return primary, variants, ref_state, w
 
+    threads, host_cores = cpu_share()
+    cpu = {}
+
+    def oracle_for_accuracy(w):
+        """The oracle's sample of the primary workload (shared by the CPU baseline, the FP64 parity
+        count and the mixed run's accuracy), computed once."""
+        if "sample" not in cpu:
+            idx = oracle_sample_indices(w.particles.n, args.cpu_sample)
+            log("timing the CPU oracle on %d threads, %d particles" % (threads, idx.size))
+            r, dt = oracle_on_sample(w, idx, threads)
+            cpu["sample"] = (idx, r, dt)
+        idx, r, _ = cpu["sample"]
+        return idx, r
+
+    want_cpu = not args.only and not args.no_cpu_baseline
+    extra = [] if args.only else [("fp64", "static"), ("fp64", "persistent"), ("mixed", "auto")]
+    primary, variants, ref_state, w = bench_workload(args.workload, args.precision, args.schedule, extra,
+                                                     oracle_for_accuracy if want_cpu else None)
+    n = primary["n"]
     out = {
         "metric": METRIC,
         "value": primary["value"],
@@ -497,37 +542,51 @@ def main():
         "data": "synthetic",
         "config": {"workload": DESCR[args.workload], "particles": n,
                    "crossings_per_step": primary["crossings_per_step"], "precision": args.precision,
-                   "schedule": sched, "layout": "cell", "launch": "hipGraph", "params": params,
-                   "block": primary["summary"]["block"], "grid": primary["summary"]["grid"]},
-        "roofline": roofline(primary, n, args.precision, args.workload, sched, mode == "timeseries",
-                             batched),
+                   "schedule": primary["schedule"], "layout": "cell", "launch": "hipGraph",
+                   "params": primary["params"], "block": primary["summary"]["block"],
+                   "grid": primary["summary"]["grid"]},
+        "roofline": roofline(primary, n, args.precision, args.workload, primary["schedule"],
+                             primary["mode"] == "timeseries", primary["batched"]),
     }
+    if want_cpu:
+        idx, r = oracle_for_accuracy(w)
+        dt = cpu["sample"][2]
+        value = float(r.ncross.astype(np.int64).sum()) / dt
+        idx1 = oracle_sample_indices(w.particles.n, max(1, args.cpu_sample // 10))
+        r1, dt1 = oracle_on_sample(w, idx1, 1)
+        v1 = float(r1.ncross.astype(np.int64).sum()) / dt1
+        out["cpu_baseline"] = {
+            "value": value, "unit": "cell-crossings/s", "cores": threads, "kind": "oracle",
+            "sample": "every %d-th particle of the workload (%d particles, %d crossings), OpenMP dynamic over "
+                      "particles on %d threads, %.1f s; 1 thread on every %d-th particle (%d): %.4g crossings/s, "
+                      "%.1f s" % (max(1, int(idx[1] - idx[0])) if idx.size > 1 else 1, idx.size,
+                                  int(r.ncross.astype(np.int64).sum()), threads, dt,
+                                  max(1, int(idx1[1] - idx1[0])) if idx1.size > 1 else 1, idx1.size, v1, dt1),
+            "host_cores_visible": host_cores, "cpu_model": host_cpu_model(),
+            "one_thread": {"value": v1, "particles": int(idx1.size), "seconds": round(dt1, 2)},
+        }
+        if ref_state is not None:
+            out["fp64_parity"] = fp64_parity(ref_state, r, idx)
+            log("FP64 parity on the oracle sample: %d of %d particles bitwise equal" % (
+                out["fp64_parity"]["bitwise_equal"], out["fp64_parity"]["particles"]))
+    def small_oracle_sample(wc):
+        """A 20,000-particle oracle sample of a further workload (its mixed run's accuracy)."""
+        idx = oracle_sample_indices(wc.particles.n, 20_000)
+        return idx, oracle_on_sample(wc, idx, threads)[0]
+
+    if not args.only and not args.no_extra_workloads and args.workload == "C4":
+        for wname, prec_list in (("C2", [("mixed", "auto")]), ("C3", [("mixed", "auto")]),
+                                 ("C5", [("mixed", "auto")]), ("C6", []), ("C7", [])):
+            pr, vr, _, _ = bench_workload(wname, "fp64", "auto", prec_list,
+                                          small_oracle_sample if (wname == "C5" and want_cpu) else None)
+            variants["%s_fp64_%s" % (wname, pr["schedule"])] = dict(
+                value=pr["value"], ms_per_step=round(pr["ms_per_step"], 4), kernel_ms=round(pr["kernel_ms"], 4),
+                crossings_per_step=pr["crossings_per_step"], launch=pr["params"],
+                roofline_frac=roofline(pr, pr["n"], "fp64", wname, pr["schedule"], pr["mode"] == "timeseries",
+                                       pr["batched"])["frac"], workload=DESCR[wname])
+            variants.update(vr)
     if variants:
         out["variants"] = variants
-    if not args.only and not args.no_cpu_baseline and not batched:
-        cores = len(os.sched_getaffinity(0))
-        threads = min(cores, 16)
-        log("timing the CPU oracle on %d threads" % threads)
-        cb = cpu_baseline(w, threads)
-        out["cpu_baseline"] = {
-            "value": cb["all_cores"]["value"], "unit": "cell-crossings/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "first %d particles of the workload, OpenMP dynamic over particles, %.1f s; "
-                      "1 thread on the first %d particles: %.4g crossings/s; host %s"
-                      % (cb["all_cores"]["particles"], cb["all_cores"]["seconds"], cb["one_core"]["particles"],
-                         cb["one_core"]["value"], host_cpu_model()),
-        }
-        if mix_state is not None and "variants" in out:
-            # the mixed-precision run against the oracle itself, on the oracle's sample
-            ro = cb["sample_result"]
-            m = ro.t.shape[0]
-            sub = {k: v[:m] for k, v in mix_state.items()}
-            acc = path_accuracy(sub, {"status": ro.status, "t": ro.t, "ncross": ro.ncross,
-                                      "path_hash": ro.path_hash}, t_release[:m])
-            acc["reference"] = "the FP64 oracle on the first %d particles" % m
-            for k, v in out["variants"].items():
-                if k.startswith("mixed_"):
-                    v["accuracy_vs_oracle"] = acc
     print(json.dumps(out), flush=True)
     return 0
 

@@ -282,11 +282,17 @@ typedef struct {
     int32_t layout;               /* the layout that ran                                         */
     int32_t block, grid;          /* launch shape of the tracking kernel                         */
     int64_t cr_ambiguous;         /* FP64 log1p/expm1/log evaluations whose correct rounding     *
-                                   * could not be decided (input within 2^-96 of a rounding      *
-                                   * boundary); the nearest double of a 2^-96-accurate value was *
-                                   * used.  Expected 0.                                          */
+                                   * was not decided: the nearest double of a 2^-96-accurate     *
+                                   * value was used.  Expected 0.  (See recheck_*.)              */
     int64_t path_records;         /* PT_PATHLINE: records counted (count pass) or written        */
     int64_t path_dropped;         /* PT_PATHLINE record pass: records outside their slot range   */
+    int64_t recheck_tracks;       /* FP64: particles whose tracking (or snapshots) met an        *
+                                   * evaluation within 2^-96 of a rounding boundary (structured  *
+                                   * inputs: arguments near 2^-53 .. 2^-50 with regular bit      *
+                                   * patterns); each was tracked again from its input state by a *
+                                   * careful pass that decides such arguments exactly.  Beyond   *
+                                   * 2^20 per call the rest keep their first results and count  *
+                                   * in cr_ambiguous.                                            */
 } pt_summary;
 
 /* Wait for the run, then fill *out.  Reports asynchronous device errors of
@@ -296,6 +302,16 @@ int pt_results(pt_run* run, pt_summary* out);
 /* Release a pt_grid* or pt_run* (waits for a run still in flight).  NULL is a
  * no-op.  A pointer that is not a live handle gives PT_ERR_BAD_HANDLE. */
 int pt_release(void* handle);
+
+/* Release everything the library holds: every live grid and run handle (waiting for the
+ * devices they use first) and the released runs kept for reuse, with their cached hipGraphs,
+ * events and device and pinned buffers.  Afterwards every earlier handle is invalid
+ * (PT_ERR_BAD_HANDLE), and the library can be used again from scratch.  Call it when no other
+ * call of this library is in progress, before the HIP runtime is torn down at process exit
+ * (the Python binding registers it with atexit), so that no HIP object of the library outlives
+ * the runtime.  Returns PT_ERR_DEVICE if a device reported an asynchronous fault while it was
+ * drained; the resources are released in any case. */
+int pt_shutdown(void);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* pt_last_error(void);

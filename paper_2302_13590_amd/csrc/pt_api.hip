@@ -18,6 +18,7 @@
 
 using namespace pt;
 
+
 static_assert(sizeof(pt_path_record) == sizeof(PathRec) && offsetof(pt_path_record, cell) == offsetof(PathRec, cell) &&
                   offsetof(pt_path_record, face) == offsetof(PathRec, face) && offsetof(pt_path_record, z) == offsetof(PathRec, z),
               "pt_path_record and the kernels' record differ");
@@ -26,15 +27,19 @@ static_assert(sizeof(pt_path_record) == sizeof(PathRec) && offsetof(pt_path_reco
 // errors
 namespace {
 
-thread_local std::string g_err;
+// Message of the last failing call of this thread (a fixed buffer: no call allocates for it).
+struct ErrBuf {
+    char s[512];
+    void clear() { s[0] = 0; }
+    const char* c_str() const { return s; }
+};
+thread_local ErrBuf g_err = {{0}};
 
 int fail(int code, const char* fmt, ...) {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_err.s, sizeof g_err.s, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return code;
 }
 
@@ -126,6 +131,8 @@ struct pt_run {
     size_t d_sort_bytes = 0;
     void* d_scan = nullptr;             // pathline count pass: tile sums of the offset scan
     size_t d_scan_bytes = 0;
+    void* d_recheck = nullptr;          // careful pass: particle and snapshot lists
+    size_t d_recheck_bytes = 0;
     int path_pass = 0;                  // 0: no pathline, 1: count pass, 2: record pass
     void* h_tables = nullptr;
     size_t h_tables_bytes = 0;
@@ -138,6 +145,9 @@ struct pt_run {
 namespace {
 
 std::vector<pt_run*> g_pool;  // released runs kept for reuse (guarded by g_mu)
+// Released runs kept: enough for a few dozen calls in flight on one stream (each keeps its
+// cached graph, events, counters and ordering buffers); pt_shutdown frees them.
+constexpr size_t kPoolMax = 32;
 
 void destroy_run(pt_run* r) {
     if (r->exec) (void)hipGraphExecDestroy(r->exec);
@@ -151,6 +161,7 @@ void destroy_run(pt_run* r) {
     if (r->h_tables) (void)hipHostFree(r->h_tables);
     if (r->d_sort) (void)hipFree(r->d_sort);
     if (r->d_scan) (void)hipFree(r->d_scan);
+    if (r->d_recheck) (void)hipFree(r->d_recheck);
     delete r;
 }
 
@@ -211,6 +222,16 @@ int ensure_sort(pt_run* r, size_t bytes) {
     r->d_sort_bytes = 0;
     HIP_TRY(hipMalloc(&r->d_sort, bytes));
     r->d_sort_bytes = bytes;
+    return PT_OK;
+}
+
+int ensure_recheck(pt_run* r, size_t bytes) {
+    if (bytes <= r->d_recheck_bytes) return PT_OK;
+    if (r->d_recheck) (void)hipFree(r->d_recheck);
+    r->d_recheck = nullptr;
+    r->d_recheck_bytes = 0;
+    HIP_TRY(hipMalloc(&r->d_recheck, bytes));
+    r->d_recheck_bytes = bytes;
     return PT_OK;
 }
 
@@ -289,12 +310,404 @@ hipError_t launch(const void* fn, dim3 grid, dim3 block, void* arg, size_t lds, 
     return hipLaunchKernel(fn, grid, block, args, lds, s);
 }
 
+
+// ---------------------------------------------------------------------------------------------
+// A tracking call in steps: the argument checks, the launch plan (kernel, shape, table and
+// ordering-buffer layout), the binding of the kernel arguments to device buffers and the launch
+// sequence.
+
+// Checks every argument of a tracking call (no device work); *dev and *n_cu describe the
+// current device.
+int check_track_args(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p, const pt_track_opts* o,
+                     int* dev, int* n_cu) {
+    if (!grids || n_grids < 1) return fail(PT_ERR_INVALID_ARG, "need at least one grid");
+    if (n_grids > 4096) return fail(PT_ERR_UNSUPPORTED, "at most 4096 grids per call");
+    for (int32_t q = 0; q < n_grids; ++q)
+        if (!grids[q] || !is_live(grids[q], kGridMagic))
+            return fail(PT_ERR_BAD_HANDLE, "grids[%d] is not a live grid handle", q);
+    if (!p || !o) return fail(PT_ERR_INVALID_ARG, "particles and options must not be NULL");
+    if (p->n < 0) return fail(PT_ERR_INVALID_ARG, "n must be >= 0");
+    if (p->n >= (int64_t(1) << 31)) return fail(PT_ERR_UNSUPPORTED, "at most 2^31 - 1 particles per call");
+    if (p->n > 0 && (!p->cell || !p->xi || !p->eta || !p->zeta || !p->t || !p->status || !p->ncross ||
+                     !p->path_hash))
+        return fail(PT_ERR_INVALID_ARG, "a particle state array is NULL");
+    if (o->mode != PT_ENDPOINT && o->mode != PT_TIMESERIES && o->mode != PT_PATHLINE)
+        return fail(PT_ERR_INVALID_ARG, "bad mode");
+    if (o->precision != PT_FP64 && o->precision != PT_MIXED) return fail(PT_ERR_INVALID_ARG, "bad precision");
+    if (o->schedule < PT_SCHED_AUTO || o->schedule > PT_SCHED_PERSISTENT)
+        return fail(PT_ERR_INVALID_ARG, "bad schedule");
+    if (o->layout < PT_LAYOUT_AUTO || o->layout > PT_LAYOUT_CELL) return fail(PT_ERR_INVALID_ARG, "bad layout");
+    if (o->direction != 1 && o->direction != -1) return fail(PT_ERR_INVALID_ARG, "direction must be +1 or -1");
+    if (o->stop_at_sink != 0 && o->stop_at_sink != 1) return fail(PT_ERR_INVALID_ARG, "stop_at_sink must be 0 or 1");
+    if (std::isnan(o->t_max)) return fail(PT_ERR_INVALID_ARG, "t_max is NaN");
+    if (o->max_steps < 1 || o->max_steps > INT32_MAX)
+        return fail(PT_ERR_INVALID_ARG, "max_steps must be in [1, 2^31-1]");
+    if (o->block != 0 && (o->block < 64 || o->block > 1024 || o->block % 64))
+        return fail(PT_ERR_INVALID_ARG, "block must be 0 or a multiple of 64 in [64, 1024]");
+    if (o->block > 256) return fail(PT_ERR_UNSUPPORTED, "block > 256 exceeds the kernels' launch bounds");
+    if (o->refill < 0 || o->refill > 64) return fail(PT_ERR_INVALID_ARG, "refill must be in [0, 64]");
+    if (o->sort < PT_SORT_AUTO || o->sort > PT_SORT_CELL) return fail(PT_ERR_INVALID_ARG, "bad sort");
+    if (o->steps_per_refill < 0 || o->blocks_per_cu < 0 || o->chunk < 0)
+        return fail(PT_ERR_INVALID_ARG, "steps_per_refill, blocks_per_cu and chunk must be >= 0");
+    if (o->precision == PT_MIXED && o->layout == PT_LAYOUT_FACES)
+        return fail(PT_ERR_UNSUPPORTED, "mixed precision needs the packed cell layout");
+    const bool ts = o->mode == PT_TIMESERIES;
+    if (ts) {
+        if (o->n_snap < 1 || !o->snap_times || !o->snap_xyz)
+            return fail(PT_ERR_INVALID_ARG, "timeseries needs snap_times, n_snap >= 1 and snap_xyz");
+        for (int32_t q = 0; q < o->n_snap; ++q) {
+            if (!is_fin(o->snap_times[q])) return fail(PT_ERR_INVALID_ARG, "snap_times[%d] is not finite", q);
+            if (q && o->snap_times[q] < o->snap_times[q - 1])
+                return fail(PT_ERR_INVALID_ARG, "snap_times must be non-decreasing");
+        }
+    }
+    const bool path = o->mode == PT_PATHLINE;
+    const bool path_count = path && o->path_count_only;
+    if (path) {
+        if (o->path_count_only != 0 && o->path_count_only != 1)
+            return fail(PT_ERR_INVALID_ARG, "path_count_only must be 0 or 1");
+        if (!o->path_offsets) return fail(PT_ERR_INVALID_ARG, "pathline needs path_offsets [n+1]");
+        if (!path_count) {
+            if (o->path_cap < 0) return fail(PT_ERR_INVALID_ARG, "path_cap must be >= 0");
+            if (o->path_cap > 0 && !o->path_records)
+                return fail(PT_ERR_INVALID_ARG, "the record pass needs path_records");
+        }
+    }
+    const int32_t n_groups = p->n_groups;
+    if (n_groups < 0) return fail(PT_ERR_INVALID_ARG, "n_groups must be >= 0");
+    const bool transient = o->n_tsteps != 0;
+    bool quad = false;
+    for (int32_t q = 0; q < n_grids; ++q) quad = quad || grids[q]->quad;
+    if (quad) {
+        if (n_grids != 1 || n_groups != 0 || transient)
+            return fail(PT_ERR_UNSUPPORTED, "a quadtree grid is tracked alone (one grid, no groups, steady flow)");
+        if (o->precision != PT_FP64) return fail(PT_ERR_UNSUPPORTED, "quadtree grids are tracked in FP64");
+        if (o->layout == PT_LAYOUT_FACES) return fail(PT_ERR_UNSUPPORTED, "quadtree grids use the packed layout");
+    }
+    if (transient) {
+        if (o->n_tsteps < 0 || !o->tstep_end) return fail(PT_ERR_INVALID_ARG, "transient flow needs n_tsteps >= 1 and tstep_end");
+        if (o->n_tsteps != n_grids) return fail(PT_ERR_INVALID_ARG, "transient flow needs one grid per time step");
+        if (n_groups != 0) return fail(PT_ERR_UNSUPPORTED, "transient flow with particle groups");
+        if (o->direction != 1) return fail(PT_ERR_UNSUPPORTED, "transient flow is tracked forward only");
+        for (int32_t q = 0; q < o->n_tsteps; ++q) {
+            if (std::isnan(o->tstep_end[q])) return fail(PT_ERR_INVALID_ARG, "tstep_end[%d] is NaN", q);
+            if (q && !(o->tstep_end[q] > o->tstep_end[q - 1]))
+                return fail(PT_ERR_INVALID_ARG, "tstep_end must be strictly increasing");
+            const GridDev& a = grids[q]->gd;
+            const GridDev& b = grids[0]->gd;
+            if (a.nx != b.nx || a.ny != b.ny || a.nz != b.nz || a.dx != b.dx || a.dy != b.dy || a.dz != b.dz ||
+                a.x0 != b.x0 || a.y0 != b.y0 || a.z0 != b.z0)
+                return fail(PT_ERR_INVALID_ARG, "the grids of the time steps must have the same geometry");
+        }
+    } else if (n_grids > 1 && n_groups == 0) {
+        return fail(PT_ERR_INVALID_ARG, "several grids need particle groups");
+    }
+    if (n_groups > 0) {
+        if (!p->group_offsets || !p->group_grid)
+            return fail(PT_ERR_INVALID_ARG, "group_offsets and group_grid must not be NULL");
+        if (p->group_offsets[0] != 0 || p->group_offsets[n_groups] != p->n)
+            return fail(PT_ERR_INVALID_ARG, "group_offsets must start at 0 and end at n");
+        for (int32_t q = 0; q < n_groups; ++q) {
+            if (p->group_offsets[q + 1] < p->group_offsets[q])
+                return fail(PT_ERR_INVALID_ARG, "group_offsets must be non-decreasing");
+            if (p->group_grid[q] < 0 || p->group_grid[q] >= n_grids)
+                return fail(PT_ERR_INVALID_ARG, "group_grid[%d] out of range", q);
+        }
+    }
+    int rc = current_device(dev, n_cu);
+    if (rc != PT_OK) return rc;
+    for (int32_t q = 0; q < n_grids; ++q)
+        if (grids[q]->device != *dev)
+            return fail(PT_ERR_INVALID_ARG, "grids[%d] lives on device %d, current is %d", q, grids[q]->device, *dev);
+    return PT_OK;
+}
+
+// What one tracking call launches, and the layout of the device buffers it needs.
+struct Plan {
+    KernelKey key;
+    const void* fn = nullptr;
+    bool ts = false, path = false, path_count = false, transient = false, batched = false, multi = false;
+    bool sort = false;
+    int32_t n_groups = 0;
+    int block = 0, grid = 0;
+    size_t lds = 0;                 // dynamic LDS of the tracking kernel
+    // per-call tables (256-byte aligned segments): grid views, group table, snapshot times, time
+    // step ends, first global cell of each grid (batched ordering)
+    size_t b_grids = 0, b_offs = 0, b_gg = 0, b_snap = 0, b_tstep = 0, b_base = 0, tables = 0;
+    // ordering by starting cell: order, rank and bucket [n] each, histogram, tile sums
+    int32_t shift = 0, nbuckets = 0, ntiles = 0;
+    size_t b_order = 0, b_hist = 0, sort_bytes = 0;
+    // pathline count pass: tile sums of the offset scan
+    int64_t scan_ntiles = 0;
+    size_t scan_bytes = 0;
+    // careful pass (FP64): capacity of the particle list and its bytes
+    int32_t recheck_cap = 0;
+    size_t recheck_bytes = 0;
+};
+
+// The plan of a checked call.  `sort_budget`: the largest ordering buffer the caller can
+// provide; PT_SORT_AUTO orders only when it fits, PT_SORT_CELL beyond it is refused.
+int make_plan(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p, const pt_track_opts* o,
+              int n_cu, size_t sort_budget, int64_t recheck_max, Plan* pl) {
+    Plan& P = *pl;
+    P.ts = o->mode == PT_TIMESERIES;
+    P.path = o->mode == PT_PATHLINE;
+    P.path_count = P.path && o->path_count_only;
+    P.transient = o->n_tsteps != 0;
+    P.n_groups = p->n_groups;
+    P.batched = P.n_groups > 0;
+    P.multi = P.batched || P.transient;   // the kernels that read a per-lane grid
+    bool quad = false;
+    for (int32_t q = 0; q < n_grids; ++q) quad = quad || grids[q]->quad;
+    P.key.precision = o->precision == PT_MIXED ? PMIX : P64;
+    P.key.layout = quad ? L_QUAD : (o->layout == PT_LAYOUT_FACES ? L_FACES : L_CELL);
+    P.key.out = P.ts ? O_SERIES : (P.path ? O_PATH : O_END);
+    P.key.batched = P.multi ? 1 : 0;
+    P.key.sched = o->schedule == PT_SCHED_STATIC ? S_STATIC : S_PERSISTENT;
+    P.fn = track_kernel(P.key);
+    P.block = o->block ? o->block : 256;
+    if (P.key.sched == S_STATIC) {
+        // a multiple of 8 chunks of blocks: chunks are dealt to the dies round robin
+        const int64_t nb = std::max<int64_t>(1, (p->n + P.block - 1) / P.block);
+        const int64_t m = (int64_t)kXcd * kDieChunk;
+        P.grid = (int)((nb + m - 1) / m * m);
+    } else {
+        int per_cu = o->blocks_per_cu;
+        if (!per_cu) {
+            int occ = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, P.fn, P.block, 0) != hipSuccess || occ < 1) {
+                (void)hipGetLastError();
+                occ = 2;
+            }
+            per_cu = occ;
+        }
+        P.grid = std::max(1, n_cu * per_cu);
+        const int64_t need = (p->n + P.block - 1) / P.block;
+        if (need < P.grid) P.grid = (int)std::max<int64_t>(1, need);
+    }
+    P.b_grids = P.multi ? align_up(sizeof(GridDev) * n_grids, 256) : 0;
+    P.b_offs = P.batched ? align_up(sizeof(int64_t) * (P.n_groups + 1), 256) : 0;
+    P.b_gg = P.batched ? align_up(sizeof(int32_t) * P.n_groups, 256) : 0;
+    P.b_snap = P.ts ? align_up(sizeof(double) * o->n_snap, 256) : 0;
+    P.b_tstep = P.transient ? align_up(sizeof(double) * o->n_tsteps, 256) : 0;
+    const bool want_sort = o->sort == PT_SORT_CELL || (o->sort == PT_SORT_AUTO && p->n >= (1 << 16));
+    if (want_sort) {
+        int64_t cells = 0;
+        for (int32_t q = 0; q < (P.batched ? n_grids : 1); ++q)
+            cells += (int64_t)grids[q]->gd.nx * grids[q]->gd.ny * grids[q]->gd.nz;
+        int shift = 0;
+        while ((cells >> shift) >= kMaxBuckets) ++shift;
+        P.shift = shift;
+        P.nbuckets = (int32_t)(cells >> shift) + 1;
+        P.ntiles = (int32_t)((P.nbuckets + kScanTile - 1) / kScanTile);
+        P.b_order = align_up(sizeof(int32_t) * (size_t)p->n, 256);
+        P.b_hist = align_up(sizeof(unsigned) * (size_t)P.nbuckets, 256);
+        P.sort_bytes = 3 * P.b_order + P.b_hist + sizeof(unsigned) * (size_t)P.ntiles;
+        P.sort = P.sort_bytes <= sort_budget;
+        if (!P.sort && o->sort == PT_SORT_CELL)
+            return fail(PT_ERR_UNSUPPORTED, "ordering %lld particles needs %zu bytes of buffer, above the %zu available",
+                        (long long)p->n, P.sort_bytes, sort_budget);
+        if (!P.sort) P.sort_bytes = 0;
+    }
+    P.b_base = (P.sort && P.batched) ? align_up(sizeof(int64_t) * n_grids, 256) : 0;
+    P.tables = P.b_grids + P.b_offs + P.b_gg + P.b_snap + P.b_tstep + P.b_base;
+    if (P.path_count) {
+        P.scan_ntiles = (p->n + kScanTile - 1) / kScanTile;
+        P.scan_bytes = sizeof(int64_t) * (size_t)std::max<int64_t>(1, P.scan_ntiles);
+    }
+    if (P.key.precision == P64 && p->n > 0) {
+        P.recheck_cap = (int32_t)std::min<int64_t>(p->n, recheck_max);
+        P.recheck_bytes = align_up(sizeof(int32_t) * (size_t)P.recheck_cap, 256);
+    }
+    // the static timeseries kernels on packed layouts keep one deferred-snapshot slot per thread
+    // in dynamic LDS; the pathline record pass stages each lane's records there
+    const bool snap_slots = P.key.out == O_SERIES && P.key.sched == S_STATIC && P.key.layout != L_FACES;
+    const size_t slot = P.key.precision == P64 ? sizeof(SnapJob<double>) : sizeof(SnapJob<float>);
+    const bool stage = P.path && !P.path_count && (reinterpret_cast<uintptr_t>(o->path_records) % 64 == 0);
+    P.lds = snap_slots ? slot * (size_t)P.block : (stage ? sizeof(PathStage) * (size_t)P.block : 0);
+    return PT_OK;
+}
+
+// The bytes of the per-call tables, segment by segment: put(offset, source, bytes).  Offsets
+// follow the plan's layout; the gaps between segments are never read.
+template <class Put>
+void write_tables(const Plan& P, const pt_grid* const* grids, int32_t n_grids, const pt_particles* p,
+                  const pt_track_opts* o, Put&& put) {
+    size_t off = 0;
+    if (P.multi) {
+        for (int32_t q = 0; q < n_grids; ++q) put(off + sizeof(GridDev) * q, &grids[q]->gd, sizeof(GridDev));
+        off += P.b_grids;
+    }
+    if (P.batched) {
+        put(off, p->group_offsets, sizeof(int64_t) * (P.n_groups + 1));
+        off += P.b_offs;
+        put(off, p->group_grid, sizeof(int32_t) * P.n_groups);
+        off += P.b_gg;
+    }
+    if (P.ts) {
+        put(off, o->snap_times, sizeof(double) * o->n_snap);
+        off += P.b_snap;
+    }
+    if (P.transient) {
+        put(off, o->tstep_end, sizeof(double) * o->n_tsteps);
+        off += P.b_tstep;
+    }
+    if (P.b_base) {
+        int64_t acc = 0;
+        for (int32_t q = 0; q < n_grids; ++q) {
+            put(off + sizeof(int64_t) * q, &acc, sizeof acc);
+            acc += (int64_t)grids[q]->gd.nx * grids[q]->gd.ny * grids[q]->gd.nz;
+        }
+    }
+}
+
+// Kernel arguments of a call whose buffers are at d_tables (P.tables bytes), d_sort
+// (P.sort_bytes), d_scan (P.scan_bytes) and d_counters.
+void bind_params(const Plan& PL, const pt_grid* const* grids, int32_t n_grids, const pt_particles* p,
+                 const pt_track_opts* o, unsigned char* d_tables, unsigned char* d_sort, int64_t* d_scan,
+                 unsigned char* d_recheck, Counters* d_counters, TrackParams& P, SortParams& SP, ScanParams& SC) {
+    std::memset(&P, 0, sizeof P);
+    std::memset(&SP, 0, sizeof SP);
+    std::memset(&SC, 0, sizeof SC);
+    size_t off = 0;
+    if (PL.multi) {
+        P.grids = reinterpret_cast<const GridDev*>(d_tables + off);
+        off += PL.b_grids;
+    }
+    if (PL.batched) {
+        P.group_offsets = reinterpret_cast<const int64_t*>(d_tables + off);
+        off += PL.b_offs;
+        P.group_grid = reinterpret_cast<const int32_t*>(d_tables + off);
+        off += PL.b_gg;
+    }
+    if (PL.ts) {
+        P.snap_times = reinterpret_cast<const double*>(d_tables + off);
+        off += PL.b_snap;
+    }
+    if (PL.transient) {
+        P.tstep_end = reinterpret_cast<const double*>(d_tables + off);
+        off += PL.b_tstep;
+    }
+    P.n = p->n;
+    P.cell = p->cell;
+    P.xi = p->xi;
+    P.eta = p->eta;
+    P.zeta = p->zeta;
+    P.t = p->t;
+    P.status = p->status;
+    P.ncross = p->ncross;
+    P.hash = p->path_hash;
+    P.n_groups = PL.n_groups;
+    P.n_grids = n_grids;
+    P.n_tsteps = PL.transient ? o->n_tsteps : 0;
+    P.g0 = grids[0]->gd;
+    P.t_max = o->t_max;
+    P.max_steps = o->max_steps;
+    P.sign = o->direction < 0 ? -1.0 : 1.0;
+    P.stop_at_sink = o->stop_at_sink;
+    P.n_snap = PL.ts ? o->n_snap : 0;
+    P.snap_xyz = PL.ts ? o->snap_xyz : nullptr;
+    P.out_xyz = o->out_xyz;
+    P.counters = d_counters;
+    if (PL.recheck_cap > 0) {
+        P.recheck_pid = reinterpret_cast<int32_t*>(d_recheck);
+        P.recheck_cap = PL.recheck_cap;
+    }
+    P.refill = o->refill ? o->refill : 1;
+    P.steps_per_refill = o->steps_per_refill ? o->steps_per_refill : 1;
+    P.chunk = o->chunk ? o->chunk : 64;
+    if (PL.path) {
+        P.path_off = o->path_offsets;
+        P.path_count = PL.path_count ? 1 : 0;
+        if (!PL.path_count) {
+            P.path_cap = o->path_cap;
+            P.path_rec = reinterpret_cast<PathRec*>(o->path_records);
+            // staged record writes need 64-byte aligned segments of the record array
+            P.path_stage = (reinterpret_cast<uintptr_t>(o->path_records) % 64 == 0) ? 1 : 0;
+        }
+    }
+    if (PL.path_count) {   // the per-particle counts become offsets (scan of path_offsets[1..n])
+        SC.v = o->path_offsets + 1;
+        SC.n = p->n;
+        SC.ntiles = PL.scan_ntiles;
+        SC.head = o->path_offsets;
+        SC.part = d_scan;
+    }
+    if (PL.sort) {
+        SP.nbuckets = PL.nbuckets;
+        SP.shift = PL.shift;
+        SP.ntiles = PL.ntiles;
+        SP.n = p->n;
+        SP.cell = p->cell;
+        SP.status = p->status;
+        SP.n_groups = PL.batched ? PL.n_groups : 0;
+        SP.group_offsets = P.group_offsets;
+        SP.group_grid = P.group_grid;
+        SP.grid_base = PL.batched ? reinterpret_cast<const int64_t*>(d_tables + (PL.tables - PL.b_base)) : nullptr;
+        SP.order = reinterpret_cast<int32_t*>(d_sort);
+        SP.rank = reinterpret_cast<unsigned*>(d_sort + PL.b_order);
+        SP.bucket = reinterpret_cast<unsigned*>(d_sort + 2 * PL.b_order);
+        SP.hist = reinterpret_cast<unsigned*>(d_sort + 3 * PL.b_order);
+        SP.part = reinterpret_cast<unsigned*>(d_sort + 3 * PL.b_order + PL.b_hist);
+        P.order = SP.order;
+    }
+}
+
+// The kernels of one call, in order (fixed capacity: no host allocation).
+struct LaunchSeq {
+    Launch v[16];
+    int n = 0;
+    void push(const void* fn, dim3 grid, dim3 block, void* arg, size_t bytes, size_t lds = 0) {
+        v[n].fn = fn;
+        v[n].grid = grid;
+        v[n].block = block;
+        v[n].arg = arg;
+        v[n].bytes = bytes;
+        v[n].lds = lds;
+        ++n;
+    }
+};
+
+// Counter reset, ordering sort, tracking kernel, pathline offset scan.  The argument blocks
+// are referenced, not copied: they must outlive the launches (or graph construction).
+void build_seq(const Plan& PL, int64_t n, Counters** cptr, TrackParams* P, SortParams* SP, ScanParams* SC,
+               LaunchSeq& seq) {
+    seq.push(reset_kernel(), dim3(1), dim3(64), cptr, sizeof *cptr);
+    if (n > 0) {
+        if (PL.sort) {
+            const unsigned nb = (unsigned)((n + 255) / 256);
+            seq.push(sort_clear_kernel(), dim3(std::min(2048u, (unsigned)(SP->nbuckets + 255) / 256)), dim3(256), SP,
+                     sizeof *SP);
+            seq.push(sort_hist_kernel(), dim3(nb), dim3(256), SP, sizeof *SP);
+            seq.push(sort_scan_tiles_kernel(), dim3((unsigned)SP->ntiles), dim3(kScanBlock), SP, sizeof *SP);
+            seq.push(sort_scan_partials_kernel(), dim3(1), dim3(kScanBlock), SP, sizeof *SP);
+            if (SP->ntiles > 1)
+                seq.push(sort_scan_add_kernel(), dim3((unsigned)SP->ntiles), dim3(kScanBlock), SP, sizeof *SP);
+            seq.push(sort_scatter_kernel(), dim3(nb), dim3(256), SP, sizeof *SP);
+        }
+        seq.push(PL.fn, dim3(PL.grid), dim3(PL.block), P, sizeof *P, PL.lds);
+        if (PL.recheck_cap > 0) {
+            // careful pass: a fixed grid that strides over the (usually empty) lists
+            const unsigned cb = 64;
+            const unsigned ct = (unsigned)std::min<int64_t>(256, (PL.recheck_cap + cb - 1) / cb);
+            seq.push(careful_kernel(PL.key), dim3(ct), dim3(cb), P, sizeof *P,
+                     P->path_stage ? sizeof(PathStage) * cb : 0);
+        }
+        if (PL.path_count)
+            seq.push(scan_tiles_kernel(), dim3((unsigned)SC->ntiles), dim3(kScanBlock), SC, sizeof *SC);
+    }
+    if (PL.path_count) {
+        seq.push(scan_partials_kernel(), dim3(1), dim3(kScanBlock), SC, sizeof *SC);
+        if (SC->ntiles > 1) seq.push(scan_add_kernel(), dim3((unsigned)SC->ntiles), dim3(kScanBlock), SC, sizeof *SC);
+    }
+}
+
 }  // namespace
 
 // =============================================================================================
 extern "C" {
 
-int pt_version(void) { return 102; }
+int pt_version(void) { return 103; }
 
 const char* pt_last_error(void) { return g_err.c_str(); }
 
@@ -547,163 +960,27 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     g_err.clear();
     if (!out) return fail(PT_ERR_INVALID_ARG, "out must not be NULL");
     *out = nullptr;
-    if (!grids || n_grids < 1) return fail(PT_ERR_INVALID_ARG, "need at least one grid");
-    if (n_grids > 4096) return fail(PT_ERR_UNSUPPORTED, "at most 4096 grids per call");
-    for (int32_t q = 0; q < n_grids; ++q)
-        if (!grids[q] || !is_live(grids[q], kGridMagic))
-            return fail(PT_ERR_BAD_HANDLE, "grids[%d] is not a live grid handle", q);
-    if (!p || !o) return fail(PT_ERR_INVALID_ARG, "particles and options must not be NULL");
-    if (p->n < 0) return fail(PT_ERR_INVALID_ARG, "n must be >= 0");
-    if (p->n >= (int64_t(1) << 31)) return fail(PT_ERR_UNSUPPORTED, "at most 2^31 - 1 particles per call");
-    if (p->n > 0 && (!p->cell || !p->xi || !p->eta || !p->zeta || !p->t || !p->status || !p->ncross ||
-                     !p->path_hash))
-        return fail(PT_ERR_INVALID_ARG, "a particle state array is NULL");
-    if (o->mode != PT_ENDPOINT && o->mode != PT_TIMESERIES && o->mode != PT_PATHLINE)
-        return fail(PT_ERR_INVALID_ARG, "bad mode");
-    if (o->precision != PT_FP64 && o->precision != PT_MIXED) return fail(PT_ERR_INVALID_ARG, "bad precision");
-    if (o->schedule < PT_SCHED_AUTO || o->schedule > PT_SCHED_PERSISTENT)
-        return fail(PT_ERR_INVALID_ARG, "bad schedule");
-    if (o->layout < PT_LAYOUT_AUTO || o->layout > PT_LAYOUT_CELL) return fail(PT_ERR_INVALID_ARG, "bad layout");
-    if (o->direction != 1 && o->direction != -1) return fail(PT_ERR_INVALID_ARG, "direction must be +1 or -1");
-    if (o->stop_at_sink != 0 && o->stop_at_sink != 1) return fail(PT_ERR_INVALID_ARG, "stop_at_sink must be 0 or 1");
-    if (std::isnan(o->t_max)) return fail(PT_ERR_INVALID_ARG, "t_max is NaN");
-    if (o->max_steps < 1 || o->max_steps > INT32_MAX)
-        return fail(PT_ERR_INVALID_ARG, "max_steps must be in [1, 2^31-1]");
-    if (o->block != 0 && (o->block < 64 || o->block > 1024 || o->block % 64))
-        return fail(PT_ERR_INVALID_ARG, "block must be 0 or a multiple of 64 in [64, 1024]");
-    if (o->block > 256) return fail(PT_ERR_UNSUPPORTED, "block > 256 exceeds the kernels' launch bounds");
-    if (o->refill < 0 || o->refill > 64) return fail(PT_ERR_INVALID_ARG, "refill must be in [0, 64]");
-    if (o->sort < PT_SORT_AUTO || o->sort > PT_SORT_CELL) return fail(PT_ERR_INVALID_ARG, "bad sort");
-    if (o->steps_per_refill < 0 || o->blocks_per_cu < 0 || o->chunk < 0)
-        return fail(PT_ERR_INVALID_ARG, "steps_per_refill, blocks_per_cu and chunk must be >= 0");
-    if (o->precision == PT_MIXED && o->layout == PT_LAYOUT_FACES)
-        return fail(PT_ERR_UNSUPPORTED, "mixed precision needs the packed cell layout");
-    const bool ts = o->mode == PT_TIMESERIES;
-    if (ts) {
-        if (o->n_snap < 1 || !o->snap_times || !o->snap_xyz)
-            return fail(PT_ERR_INVALID_ARG, "timeseries needs snap_times, n_snap >= 1 and snap_xyz");
-        for (int32_t q = 0; q < o->n_snap; ++q) {
-            if (!is_fin(o->snap_times[q])) return fail(PT_ERR_INVALID_ARG, "snap_times[%d] is not finite", q);
-            if (q && o->snap_times[q] < o->snap_times[q - 1])
-                return fail(PT_ERR_INVALID_ARG, "snap_times must be non-decreasing");
-        }
-    }
-    const bool path = o->mode == PT_PATHLINE;
-    const bool path_count = path && o->path_count_only;
-    if (path) {
-        if (o->path_count_only != 0 && o->path_count_only != 1)
-            return fail(PT_ERR_INVALID_ARG, "path_count_only must be 0 or 1");
-        if (!o->path_offsets) return fail(PT_ERR_INVALID_ARG, "pathline needs path_offsets [n+1]");
-        if (!path_count) {
-            if (o->path_cap < 0) return fail(PT_ERR_INVALID_ARG, "path_cap must be >= 0");
-            if (o->path_cap > 0 && !o->path_records)
-                return fail(PT_ERR_INVALID_ARG, "the record pass needs path_records");
-        }
-    }
-    const int32_t n_groups = p->n_groups;
-    if (n_groups < 0) return fail(PT_ERR_INVALID_ARG, "n_groups must be >= 0");
-    const bool transient = o->n_tsteps != 0;
-    bool quad = false;
-    for (int32_t q = 0; q < n_grids; ++q) quad = quad || grids[q]->quad;
-    if (quad) {
-        if (n_grids != 1 || n_groups != 0 || transient)
-            return fail(PT_ERR_UNSUPPORTED, "a quadtree grid is tracked alone (one grid, no groups, steady flow)");
-        if (o->precision != PT_FP64) return fail(PT_ERR_UNSUPPORTED, "quadtree grids are tracked in FP64");
-        if (o->layout == PT_LAYOUT_FACES) return fail(PT_ERR_UNSUPPORTED, "quadtree grids use the packed layout");
-    }
-    if (transient) {
-        if (o->n_tsteps < 0 || !o->tstep_end) return fail(PT_ERR_INVALID_ARG, "transient flow needs n_tsteps >= 1 and tstep_end");
-        if (o->n_tsteps != n_grids) return fail(PT_ERR_INVALID_ARG, "transient flow needs one grid per time step");
-        if (n_groups != 0) return fail(PT_ERR_UNSUPPORTED, "transient flow with particle groups");
-        if (o->direction != 1) return fail(PT_ERR_UNSUPPORTED, "transient flow is tracked forward only");
-        for (int32_t q = 0; q < o->n_tsteps; ++q) {
-            if (std::isnan(o->tstep_end[q])) return fail(PT_ERR_INVALID_ARG, "tstep_end[%d] is NaN", q);
-            if (q && !(o->tstep_end[q] > o->tstep_end[q - 1]))
-                return fail(PT_ERR_INVALID_ARG, "tstep_end must be strictly increasing");
-            const GridDev& a = grids[q]->gd;
-            const GridDev& b = grids[0]->gd;
-            if (a.nx != b.nx || a.ny != b.ny || a.nz != b.nz || a.dx != b.dx || a.dy != b.dy || a.dz != b.dz ||
-                a.x0 != b.x0 || a.y0 != b.y0 || a.z0 != b.z0)
-                return fail(PT_ERR_INVALID_ARG, "the grids of the time steps must have the same geometry");
-        }
-    } else if (n_grids > 1 && n_groups == 0) {
-        return fail(PT_ERR_INVALID_ARG, "several grids need particle groups");
-    }
-    if (n_groups > 0) {
-        if (!p->group_offsets || !p->group_grid)
-            return fail(PT_ERR_INVALID_ARG, "group_offsets and group_grid must not be NULL");
-        if (p->group_offsets[0] != 0 || p->group_offsets[n_groups] != p->n)
-            return fail(PT_ERR_INVALID_ARG, "group_offsets must start at 0 and end at n");
-        for (int32_t q = 0; q < n_groups; ++q) {
-            if (p->group_offsets[q + 1] < p->group_offsets[q])
-                return fail(PT_ERR_INVALID_ARG, "group_offsets must be non-decreasing");
-            if (p->group_grid[q] < 0 || p->group_grid[q] >= n_grids)
-                return fail(PT_ERR_INVALID_ARG, "group_grid[%d] out of range", q);
-        }
-    }
     int dev = 0, n_cu = 0;
-    int rc = current_device(&dev, &n_cu);
+    int rc = check_track_args(grids, n_grids, p, o, &dev, &n_cu);
     if (rc != PT_OK) return rc;
-    for (int32_t q = 0; q < n_grids; ++q)
-        if (grids[q]->device != dev)
-            return fail(PT_ERR_INVALID_ARG, "grids[%d] lives on device %d, current is %d", q, grids[q]->device, dev);
+    Plan PL;
+    rc = make_plan(grids, n_grids, p, o, n_cu, SIZE_MAX, kRecheckTracksMax, &PL);
+    if (rc != PT_OK) return rc;
 
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     pt_run* r = nullptr;
     rc = new_run(dev, &r);
     if (rc != PT_OK) return rc;
     r->stream = s;
-
-    // kernel choice and launch shape
-    const bool batched = n_groups > 0;
-    const bool multi = batched || transient;   // the kernels that read a per-lane grid
-    KernelKey key;
-    key.precision = o->precision == PT_MIXED ? PMIX : P64;
-    key.layout = quad ? L_QUAD : (o->layout == PT_LAYOUT_FACES ? L_FACES : L_CELL);
-    key.out = ts ? O_SERIES : (path ? O_PATH : O_END);
-    key.batched = multi ? 1 : 0;
-    key.sched = o->schedule == PT_SCHED_STATIC ? S_STATIC : S_PERSISTENT;
-    const void* fn = track_kernel(key);
-    const int block = o->block ? o->block : 256;
-    int grid;
-    if (key.sched == S_STATIC) {
-        // a multiple of 8 chunks of blocks: chunks are dealt to the dies round robin
-        const int64_t nb = std::max<int64_t>(1, (p->n + block - 1) / block);
-        const int64_t m = (int64_t)kXcd * kDieChunk;
-        grid = (int)((nb + m - 1) / m * m);
-    } else {
-        int per_cu = o->blocks_per_cu;
-        if (!per_cu) {
-            int occ = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, block, 0) != hipSuccess || occ < 1) {
-                (void)hipGetLastError();
-                occ = 2;
-            }
-            per_cu = occ;
-        }
-        grid = std::max(1, n_cu * per_cu);
-        const int64_t need = (p->n + block - 1) / block;
-        if (need < grid) grid = (int)std::max<int64_t>(1, need);
-    }
-    r->sched = key.sched == S_STATIC ? PT_SCHED_STATIC : PT_SCHED_PERSISTENT;
-    r->layout = key.layout == L_FACES ? PT_LAYOUT_FACES : PT_LAYOUT_CELL;   // quadtree: its packed records
-    r->block = block;
-    r->grid = grid;
-    r->path_pass = path ? (path_count ? 1 : 2) : 0;
+    r->sched = PL.key.sched == S_STATIC ? PT_SCHED_STATIC : PT_SCHED_PERSISTENT;
+    r->layout = PL.key.layout == L_FACES ? PT_LAYOUT_FACES : PT_LAYOUT_CELL;   // quadtree: its packed records
+    r->block = PL.block;
+    r->grid = PL.grid;
+    r->path_pass = PL.path ? (PL.path_count ? 1 : 2) : 0;
 
     // per-run tables: grid views, group table, snapshot times
-    const size_t b_grids = multi ? align_up(sizeof(GridDev) * n_grids, 256) : 0;
-    const size_t b_offs = batched ? align_up(sizeof(int64_t) * (n_groups + 1), 256) : 0;
-    const size_t b_gg = batched ? align_up(sizeof(int32_t) * n_groups, 256) : 0;
-    const size_t b_snap = ts ? align_up(sizeof(double) * o->n_snap, 256) : 0;
-    const size_t b_tstep = transient ? align_up(sizeof(double) * o->n_tsteps, 256) : 0;
-    const bool sort = o->sort == PT_SORT_CELL || (o->sort == PT_SORT_AUTO && p->n >= (1 << 16));
-    const size_t b_base = (sort && batched) ? align_up(sizeof(int64_t) * n_grids, 256) : 0;
-    const size_t total = b_grids + b_offs + b_gg + b_snap + b_tstep + b_base;
-    TrackParams P;
-    std::memset(&P, 0, sizeof P);
-    if (total) {
-        rc = ensure_tables(r, total);
+    if (PL.tables) {
+        rc = ensure_tables(r, PL.tables);
         if (rc != PT_OK) {
             destroy_run(r);
             return rc;
@@ -711,177 +988,60 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
         // the previous use of this pinned buffer has completed: runs are reused only after
         // pt_release, which waits for them
         unsigned char* h = static_cast<unsigned char*>(r->h_tables);
-        unsigned char* dd = static_cast<unsigned char*>(r->d_tables);
-        size_t off = 0;
-        if (multi) {
-            GridDev* hg = reinterpret_cast<GridDev*>(h + off);
-            for (int32_t q = 0; q < n_grids; ++q) hg[q] = grids[q]->gd;
-            P.grids = reinterpret_cast<const GridDev*>(dd + off);
-            off += b_grids;
-        }
-        if (batched) {
-            std::memcpy(h + off, p->group_offsets, sizeof(int64_t) * (n_groups + 1));
-            P.group_offsets = reinterpret_cast<const int64_t*>(dd + off);
-            off += b_offs;
-            std::memcpy(h + off, p->group_grid, sizeof(int32_t) * n_groups);
-            P.group_grid = reinterpret_cast<const int32_t*>(dd + off);
-            off += b_gg;
-        }
-        if (ts) {
-            std::memcpy(h + off, o->snap_times, sizeof(double) * o->n_snap);
-            P.snap_times = reinterpret_cast<const double*>(dd + off);
-            off += b_snap;
-        }
-        if (transient) {
-            std::memcpy(h + off, o->tstep_end, sizeof(double) * o->n_tsteps);
-            P.tstep_end = reinterpret_cast<const double*>(dd + off);
-            off += b_tstep;
-        }
-        if (b_base) {
-            int64_t* base = reinterpret_cast<int64_t*>(h + off);
-            int64_t acc = 0;
-            for (int32_t q = 0; q < n_grids; ++q) {
-                base[q] = acc;
-                acc += (int64_t)grids[q]->gd.nx * grids[q]->gd.ny * grids[q]->gd.nz;
-            }
-            off += b_base;
-        }
-        hipError_t e = hipMemcpyAsync(r->d_tables, r->h_tables, total, hipMemcpyHostToDevice, s);
+        write_tables(PL, grids, n_grids, p, o,
+                     [&](size_t off, const void* src, size_t bytes) { std::memcpy(h + off, src, bytes); });
+        hipError_t e = hipMemcpyAsync(r->d_tables, r->h_tables, PL.tables, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             destroy_run(r);
             return fail(hip_code(e), "table upload failed: %s", hipGetErrorString(e));
         }
     }
-    P.n = p->n;
-    P.cell = p->cell;
-    P.xi = p->xi;
-    P.eta = p->eta;
-    P.zeta = p->zeta;
-    P.t = p->t;
-    P.status = p->status;
-    P.ncross = p->ncross;
-    P.hash = p->path_hash;
-    P.n_groups = n_groups;
-    P.n_grids = n_grids;
-    P.n_tsteps = transient ? o->n_tsteps : 0;
-    P.g0 = grids[0]->gd;
-    P.t_max = o->t_max;
-    P.max_steps = o->max_steps;
-    P.sign = o->direction < 0 ? -1.0 : 1.0;
-    P.stop_at_sink = o->stop_at_sink;
-    P.n_snap = ts ? o->n_snap : 0;
-    P.snap_xyz = ts ? o->snap_xyz : nullptr;
-    P.out_xyz = o->out_xyz;
-    P.counters = r->d_counters;
-    P.refill = o->refill ? o->refill : 1;
-    P.steps_per_refill = o->steps_per_refill ? o->steps_per_refill : 1;
-    P.chunk = o->chunk ? o->chunk : 64;
-    if (path) {
-        P.path_off = o->path_offsets;
-        P.path_count = path_count ? 1 : 0;
-        if (!path_count) {
-            P.path_cap = o->path_cap;
-            P.path_rec = reinterpret_cast<PathRec*>(o->path_records);
-            // staged record writes need 64-byte aligned segments of the record array
-            P.path_stage = (reinterpret_cast<uintptr_t>(o->path_records) % 64 == 0) ? 1 : 0;
-        }
-    }
-
-    // count pass: the per-particle counts become offsets (scan of path_offsets[1..n])
-    ScanParams SC;
-    std::memset(&SC, 0, sizeof SC);
-    if (path_count) {
-        SC.v = o->path_offsets + 1;
-        SC.n = p->n;
-        SC.ntiles = (p->n + kScanTile - 1) / kScanTile;
-        SC.head = o->path_offsets;
-        rc = ensure_scan(r, sizeof(int64_t) * (size_t)std::max<int64_t>(1, SC.ntiles));
+    if (PL.path_count) {
+        rc = ensure_scan(r, PL.scan_bytes);
         if (rc != PT_OK) {
             destroy_run(r);
             return rc;
         }
-        SC.part = static_cast<int64_t*>(r->d_scan);
     }
-
-    // spatial ordering of the particles (counting sort by starting cell)
+    if (PL.sort) {
+        rc = ensure_sort(r, PL.sort_bytes);
+        if (rc != PT_OK) {
+            destroy_run(r);
+            return rc;
+        }
+    }
+    if (PL.recheck_bytes) {
+        rc = ensure_recheck(r, PL.recheck_bytes);
+        if (rc != PT_OK) {
+            destroy_run(r);
+            return rc;
+        }
+    }
+    TrackParams P;
     SortParams SP;
-    std::memset(&SP, 0, sizeof SP);
-    if (sort) {
-        int64_t cells = 0;
-        for (int32_t q = 0; q < (batched ? n_grids : 1); ++q)
-            cells += (int64_t)grids[q]->gd.nx * grids[q]->gd.ny * grids[q]->gd.nz;
-        int shift = 0;
-        while ((cells >> shift) >= kMaxBuckets) ++shift;
-        SP.nbuckets = (int32_t)(cells >> shift) + 1;
-        SP.shift = shift;
-        SP.ntiles = (int32_t)((SP.nbuckets + kScanTile - 1) / kScanTile);
-        const size_t b_order = align_up(sizeof(int32_t) * (size_t)p->n, 256);
-        const size_t b_hist = align_up(sizeof(unsigned) * (size_t)SP.nbuckets, 256);
-        rc = ensure_sort(r, 3 * b_order + b_hist + sizeof(unsigned) * (size_t)SP.ntiles);
-        if (rc != PT_OK) {
-            destroy_run(r);
-            return rc;
-        }
-        SP.n = p->n;
-        SP.cell = p->cell;
-        SP.status = p->status;
-        SP.n_groups = batched ? n_groups : 0;
-        SP.group_offsets = P.group_offsets;
-        SP.group_grid = P.group_grid;
-        SP.grid_base = batched ? reinterpret_cast<const int64_t*>(static_cast<unsigned char*>(r->d_tables) +
-                                                                  (total - b_base))
-                               : nullptr;
-        SP.order = static_cast<int32_t*>(r->d_sort);
-        SP.rank = reinterpret_cast<unsigned*>(static_cast<unsigned char*>(r->d_sort) + b_order);
-        SP.bucket = reinterpret_cast<unsigned*>(static_cast<unsigned char*>(r->d_sort) + 2 * b_order);
-        SP.hist = reinterpret_cast<unsigned*>(static_cast<unsigned char*>(r->d_sort) + 3 * b_order);
-        SP.part = reinterpret_cast<unsigned*>(static_cast<unsigned char*>(r->d_sort) + 3 * b_order + b_hist);
-        P.order = SP.order;
-    }
+    ScanParams SC;
+    bind_params(PL, grids, n_grids, p, o, static_cast<unsigned char*>(r->d_tables),
+                static_cast<unsigned char*>(r->d_sort), static_cast<int64_t*>(r->d_scan),
+                static_cast<unsigned char*>(r->d_recheck), r->d_counters, P, SP, SC);
     Counters* cptr = r->d_counters;
-    std::vector<Launch> seq;
-    seq.push_back({reset_kernel(), dim3(1), dim3(64), &cptr, sizeof cptr});
-    if (p->n > 0) {
-        if (sort) {
-            const unsigned nb = (unsigned)((p->n + 255) / 256);
-            seq.push_back({sort_clear_kernel(), dim3(std::min(2048u, (unsigned)(SP.nbuckets + 255) / 256)),
-                           dim3(256), &SP, sizeof SP});
-            seq.push_back({sort_hist_kernel(), dim3(nb), dim3(256), &SP, sizeof SP});
-            seq.push_back({sort_scan_tiles_kernel(), dim3((unsigned)SP.ntiles), dim3(kScanBlock), &SP, sizeof SP});
-            seq.push_back({sort_scan_partials_kernel(), dim3(1), dim3(kScanBlock), &SP, sizeof SP});
-            if (SP.ntiles > 1)
-                seq.push_back({sort_scan_add_kernel(), dim3((unsigned)SP.ntiles), dim3(kScanBlock), &SP, sizeof SP});
-            seq.push_back({sort_scatter_kernel(), dim3(nb), dim3(256), &SP, sizeof SP});
-        }
-        // the static timeseries kernels on packed layouts keep one deferred-snapshot slot per
-        // thread in dynamic LDS
-        const bool snap_slots = key.out == O_SERIES && key.sched == S_STATIC && key.layout != L_FACES;
-        const size_t slot = key.precision == P64 ? sizeof(SnapJob<double>) : sizeof(SnapJob<float>);
-        // the pathline record pass stages each lane's records in dynamic LDS
-        const size_t lds = snap_slots ? slot * (size_t)block : (P.path_stage ? sizeof(PathStage) * (size_t)block : 0);
-        seq.push_back({fn, dim3(grid), dim3(block), &P, sizeof P, lds});
-        if (path_count) seq.push_back({scan_tiles_kernel(), dim3((unsigned)SC.ntiles), dim3(kScanBlock), &SC, sizeof SC});
-    }
-    if (path_count) {
-        seq.push_back({scan_partials_kernel(), dim3(1), dim3(kScanBlock), &SC, sizeof SC});
-        if (SC.ntiles > 1) seq.push_back({scan_add_kernel(), dim3((unsigned)SC.ntiles), dim3(kScanBlock), &SC, sizeof SC});
-    }
+    LaunchSeq seq;
+    build_seq(PL, p->n, &cptr, &P, &SP, &SC, seq);
 
     hipError_t e = hipEventRecord(r->ev0, s);
     if (e == hipSuccess) {
         if (o->use_graph) {
             // key: every launch's function, shape, dynamic LDS and argument bytes
             std::vector<unsigned char> gkey;
-            for (const Launch& L : seq) {
-                const size_t bytes = L.bytes;
+            for (int q = 0; q < seq.n; ++q) {
+                const Launch& L = seq.v[q];
                 const unsigned char* a = static_cast<const unsigned char*>(L.arg);
                 const unsigned char* f = reinterpret_cast<const unsigned char*>(&L.fn);
                 gkey.insert(gkey.end(), f, f + sizeof L.fn);
                 const unsigned dims[3] = {L.grid.x, L.block.x, (unsigned)L.lds};
                 const unsigned char* d = reinterpret_cast<const unsigned char*>(dims);
                 gkey.insert(gkey.end(), d, d + sizeof dims);
-                gkey.insert(gkey.end(), a, a + bytes);
+                gkey.insert(gkey.end(), a, a + L.bytes);
             }
             if (!r->exec || r->graph_key != gkey) {
                 if (r->exec) {
@@ -893,15 +1053,15 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
                 hipGraph_t gr = nullptr;
                 e = hipGraphCreate(&gr, 0);
                 hipGraphNode_t prev = nullptr;
-                for (size_t q = 0; e == hipSuccess && q < seq.size(); ++q) {
-                    void* args[] = {seq[q].arg};
+                for (int q = 0; e == hipSuccess && q < seq.n; ++q) {
+                    void* args[] = {seq.v[q].arg};
                     hipKernelNodeParams kp;
                     std::memset(&kp, 0, sizeof kp);
-                    kp.func = const_cast<void*>(seq[q].fn);
-                    kp.gridDim = seq[q].grid;
-                    kp.blockDim = seq[q].block;
+                    kp.func = const_cast<void*>(seq.v[q].fn);
+                    kp.gridDim = seq.v[q].grid;
+                    kp.blockDim = seq.v[q].block;
                     kp.kernelParams = args;
-                    kp.sharedMemBytes = (unsigned)seq[q].lds;
+                    kp.sharedMemBytes = (unsigned)seq.v[q].lds;
                     hipGraphNode_t node = nullptr;
                     e = hipGraphAddKernelNode(&node, gr, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
                     prev = node;
@@ -917,8 +1077,8 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
             }
             if (e == hipSuccess) e = hipGraphLaunch(r->exec, s);
         } else {
-            for (size_t q = 0; e == hipSuccess && q < seq.size(); ++q)
-                e = launch(seq[q].fn, seq[q].grid, seq[q].block, seq[q].arg, seq[q].lds, s);
+            for (int q = 0; e == hipSuccess && q < seq.n; ++q)
+                e = launch(seq.v[q].fn, seq.v[q].grid, seq.v[q].block, seq.v[q].arg, seq.v[q].lds, s);
         }
     }
     if (e == hipSuccess) e = hipEventRecord(r->ev1, s);
@@ -958,12 +1118,62 @@ int pt_results(pt_run* r, pt_summary* out) {
     out->block = r->block;
     out->grid = r->grid;
     out->cr_ambiguous = (int64_t)c.cr_ambiguous;
+    out->recheck_tracks = (int64_t)c.recheck_tracks;
     if (r->path_pass == 1) out->path_records = out->crossings;
     if (r->path_pass == 2) {
         out->path_dropped = (int64_t)c.path_dropped;
         out->path_records = out->crossings - out->path_dropped;
     }
     return PT_OK;
+}
+
+int pt_shutdown(void) {
+    g_err.clear();
+    std::vector<void*> live;
+    std::vector<pt_run*> pool;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        live.assign(g_live.begin(), g_live.end());
+        g_live.clear();
+        pool.swap(g_pool);
+    }
+    // wait for every device this library has work or memory on, then free everything
+    std::vector<int> devs;
+    auto note = [&](int d) {
+        if (std::find(devs.begin(), devs.end(), d) == devs.end()) devs.push_back(d);
+    };
+    for (void* h : live) note(*reinterpret_cast<uint32_t*>(h) == kGridMagic ? static_cast<pt_grid*>(h)->device
+                                                                             : static_cast<pt_run*>(h)->device);
+    for (pt_run* r : pool) note(r->device);
+    int cur = 0;
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    int rc = PT_OK;
+    for (int d : devs) {
+        hipError_t e = hipSetDevice(d);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            rc = fail(hip_code(e), "device %d failed before shutdown: %s", d, hipGetErrorString(e));
+        }
+    }
+    for (void* h : live) {
+        if (*reinterpret_cast<uint32_t*>(h) == kGridMagic) {
+            pt_grid* g = static_cast<pt_grid*>(h);
+            (void)hipSetDevice(g->device);
+            free_grid(g);
+        } else {
+            pt_run* r = static_cast<pt_run*>(h);
+            (void)hipSetDevice(r->device);
+            destroy_run(r);
+        }
+    }
+    for (pt_run* r : pool) {
+        (void)hipSetDevice(r->device);
+        destroy_run(r);
+    }
+    if (have_cur) (void)hipSetDevice(cur);
+    (void)hipGetLastError();
+    return rc;
 }
 
 int pt_release(void* h) {
@@ -985,7 +1195,7 @@ int pt_release(void* h) {
         return fail(hip_code(e), "run failed on the device: %s", hipGetErrorString(e));
     }
     std::lock_guard<std::mutex> lk(g_mu);
-    if (g_pool.size() < 8) g_pool.push_back(r);
+    if (g_pool.size() < kPoolMax) g_pool.push_back(r);
     else destroy_run(r);
     return PT_OK;
 }

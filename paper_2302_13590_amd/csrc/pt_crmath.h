@@ -148,6 +148,70 @@ PT_CR_HD bool round_test(dd v, double eps, double* out) {
 constexpr double kEpsQuick = 0x1p-68;
 constexpr double kEpsAccurate = 0x1p-96;
 
+// What an evaluation does when the accurate phase cannot decide the rounding either.
+//   CR_EXACT: arguments below 2^-40 are decided from exact parts (below); any other such argument
+//             (closer than 2^-96 to a midpoint, not expected to occur) is counted in `ambiguous`.
+//   CR_FLAG:  every such argument is counted in `ambiguous` and the nearest double of the accurate
+//             value is returned -- for code that re-runs the flagged work with CR_EXACT elsewhere
+//             (the exact path needs registers that a hot loop does not have).
+enum CrMode { CR_EXACT = 0, CR_FLAG = 1 };
+
+// ----------------------------------------------------------------------------------- small arguments
+// For 2^-60 <= |x| < 2^-40, expm1(x) = x + x^2/2 + ... and log1p(x) = x - x^2/2 + ... lie within a
+// few ulps of x, and for x near 2^-53 .. 2^-50 the x^2/2 term is close to half an ulp of x: the
+// value can sit within 2^-100 of a rounding midpoint for structural reasons (x with a regular bit
+// pattern, such as values just below a power of two), which the 2^-96 accurate phase cannot
+// decide.  When the accurate phase fails on such an argument, the value is summed from exact
+// parts instead and the rounding is decided by an exact comparison with the midpoint.
+
+// RN(s + th + tl) for a double s, a tail th with |th| <= |s| whose sum with s is formed exactly,
+// and tl, known to within err, far below ulp(s).
+PT_CR_HD double round_sum3(double s, double th, double tl, double err, unsigned* ambiguous) {
+    const dd w = fast_two_sum(s, th);                     // s + th = w.h + w.l exactly
+    // the neighbour of w.h on w.l's side (w.h finite and non-zero here): one step of the
+    // magnitude's bit pattern away from or towards zero
+    int64_t bits;
+    __builtin_memcpy(&bits, &w.h, sizeof bits);
+    bits += ((w.l > 0.0) == (w.h > 0.0)) ? 1 : -1;
+    double nb;
+    __builtin_memcpy(&nb, &bits, sizeof nb);
+    const double m = 0.5 * (nb - w.h);                    // the midpoint on w.l's side, signed (exact)
+    if (!(fabs(w.l) >= 0.5 * fabs(m))) return w.h;        // tl cannot carry the sum to the midpoint
+    const double g = w.l - m;                             // exact (Sterbenz)
+    const double d = g + tl;                              // its sign is the side of the midpoint
+    if (m > 0.0 ? d > err : d < -err) return nb;
+    if (m > 0.0 ? d < -err : d > err) return w.h;
+    *ambiguous += 1u;
+    return (m > 0.0 ? d >= 0.0 : d <= 0.0) ? nb : w.h;
+}
+
+// expm1(x) for 2^-60 <= |x| < 2^-40: x + x^2/2 + x^3/6 + x^4/24, truncation below 2^-166 |x|.
+// x^2 = p + pe and x p = q + qe exactly; x^3/6 as a double-double to ~2^-100 of itself.
+PT_CR_HD double expm1_small(double x, unsigned* ambiguous) {
+    const double p = x * x, pe = fma(x, x, -p);
+    const double q = x * p, qe = fma(x, p, -q);
+    const double c3 = q / 6.0;
+    const double c3l = ((fma(-c3, 6.0, q) + qe) + x * pe) / 6.0;
+    const double c4 = (p * p) / 24.0;
+    const dd v = two_sum(x, 0.5 * p);                     // x + x^2/2 (high part) exactly
+    const dd t = two_sum(v.l, c3);
+    const double tl = t.l + ((0.5 * pe + c3l) + c4);
+    return round_sum3(v.h, t.h, tl, 0x1p-140 * fabs(x), ambiguous);
+}
+
+// log1p(x) for 2^-60 <= |x| < 2^-40: x - x^2/2 + x^3/3 - x^4/4, truncation below 2^-160 |x|.
+PT_CR_HD double log1p_small(double x, unsigned* ambiguous) {
+    const double p = x * x, pe = fma(x, x, -p);
+    const double q = x * p, qe = fma(x, p, -q);
+    const double c3 = q / 3.0;
+    const double c3l = ((fma(-c3, 3.0, q) + qe) + x * pe) / 3.0;
+    const double c4 = -0.25 * (p * p);
+    const dd v = two_sum(x, -0.5 * p);
+    const dd t = two_sum(v.l, c3);
+    const double tl = t.l + ((-0.5 * pe + c3l) + c4);
+    return round_sum3(v.h, t.h, tl, 0x1p-140 * fabs(x), ambiguous);
+}
+
 // ----------------------------------------------------------------------------------- log
 
 struct LogRed {
@@ -253,22 +317,29 @@ PT_CR_HD dd log1p_series_accurate(dd r) {
     return dd_mul(r, S);
 }
 
-// Accurate phase: it runs for about one evaluation in 2^15.
+// Accurate phase: it runs for about one evaluation in 2^15.  With CR_EXACT, a log1p argument x
+// below 2^-40 (y = 1 + x carried as yh + yl) that it cannot decide is decided from exact parts.
+template <int M>
 PT_CR_COLD double log_accurate(double yh, double yl, unsigned* ambiguous) {
     const LogRed R = log_reduce_accurate(yh, yl);
     const dd a = log_sum_accurate(R, log1p_series_accurate(R.r));
     double out;
     if (round_test(a, kEpsAccurate, &out)) return out;
+    if (M == CR_EXACT) {
+        const double x = (yh - 1.0) + yl;   // exact when y = 1 + x was formed from a double x this small
+        if (fabs(x) < 0x1p-40 && fabs(yh - 1.0) <= 0x1p-39) return log1p_small(x, ambiguous);
+    }
     *ambiguous += 1u;
     return a.h + a.l;
 }
 
+template <int M = CR_EXACT>
 PT_CR_HD double log_dd_cr(double yh, double yl, unsigned* ambiguous) {
     const LogRed R = log_reduce(yh, yl);
     double out;
     const dd q = log_sum(R, log1p_series_quick(R.r));
     if (round_test(q, kEpsQuick, &out)) return out;
-    return log_accurate(yh, yl, ambiguous);
+    return log_accurate<M>(yh, yl, ambiguous);
 }
 
 // Inputs of log1p that need no reduction: stores the result and returns true.
@@ -298,18 +369,20 @@ PT_CR_HD bool log_special(double x, double* out) {
 }
 
 // Correctly rounded log1p(x).
+template <int M = CR_EXACT>
 PT_CR_HD double log1p_cr(double x, unsigned* ambiguous) {
     double out;
     if (log1p_special(x, &out)) return out;
     const dd y = two_sum(1.0, x);       // 1 + x exactly
-    return log_dd_cr(y.h, y.l, ambiguous);
+    return log_dd_cr<M>(y.h, y.l, ambiguous);
 }
 
 // Correctly rounded log(x).
+template <int M = CR_EXACT>
 PT_CR_HD double log_cr(double x, unsigned* ambiguous) {
     double out;
     if (log_special(x, &out)) return out;
-    return log_dd_cr(x, 0.0, ambiguous);
+    return log_dd_cr<M>(x, 0.0, ambiguous);
 }
 
 // ----------------------------------------------------------------------------------- expm1
@@ -386,6 +459,7 @@ PT_CR_HD dd expm1_combine(const ExpRed& R, dd q, int s) {
 }
 
 // Accurate phase of expm1 (x in the main range).
+template <int M>
 PT_CR_COLD double expm1_accurate(double x, unsigned* ambiguous) {
     const ExpRed R = exp_reduce(x);
     const int s = (R.k > 1000) ? 2 : 0;
@@ -393,11 +467,13 @@ PT_CR_COLD double expm1_accurate(double x, unsigned* ambiguous) {
     const dd a = expm1_combine<false>(R, expm1_series_accurate(R.r), s);
     double out;
     if (round_test(a, kEpsAccurate, &out)) return out * back;
+    if (M == CR_EXACT && fabs(x) < 0x1p-40) return expm1_small(x, ambiguous);
     *ambiguous += 1u;
     return (a.h + a.l) * back;
 }
 
 // Correctly rounded expm1(x).
+template <int M = CR_EXACT>
 PT_CR_HD double expm1_cr(double x, unsigned* ambiguous) {
     if (!(x == x)) return x;
     if (fabs(x) < 0x1p-60) return x;     // expm1(x) = x (1 + x/2 + ...) rounds to x
@@ -409,7 +485,7 @@ PT_CR_HD double expm1_cr(double x, unsigned* ambiguous) {
     double out;
     const dd q = expm1_combine<true>(R, expm1_series_quick(R.r), s);
     if (round_test(q, kEpsQuick, &out)) return out * back;
-    return expm1_accurate(x, ambiguous);
+    return expm1_accurate<M>(x, ambiguous);
 }
 
 }  // namespace ptcr

@@ -86,7 +86,8 @@ struct Counters {
     unsigned long long cr_ambiguous;  // correctly rounded evaluations left undecided
     unsigned long long queue[kXcd];   // next slot handed out in each die's segment
     unsigned long long path_dropped;  // pathline records outside their slot range
-    unsigned long long pad[13];
+    unsigned long long recheck_tracks;  // particles handed to the careful pass (may exceed its capacity)
+    unsigned long long pad[12];
 };
 static_assert(sizeof(Counters) == 32 * 8, "Counters is 32 words");
 
@@ -96,6 +97,9 @@ struct PathRec {
     int32_t cell, face;
 };
 static_assert(sizeof(PathRec) == 40, "PathRec is 40 bytes");
+
+// Capacity of the careful pass's particle list in pt_track.
+constexpr int64_t kRecheckTracksMax = (int64_t)1 << 20;
 
 struct TrackParams {
     int64_t n;
@@ -144,6 +148,13 @@ struct TrackParams {
     int32_t n_tsteps;
     int32_t pad_ts;
     const double* tstep_end;
+    // Careful pass (FP64).  A correctly rounded evaluation that the accurate phase cannot decide
+    // (a value within 2^-96 of a rounding midpoint) is not settled in the tracking kernels, whose
+    // registers are sized for the common path: the particle's pid goes to recheck_pid and it is
+    // tracked again from its input state by the careful kernel.
+    int32_t* recheck_pid;
+    int32_t recheck_cap;          // entries of recheck_pid (0: no careful pass)
+    int32_t pad_recheck;
 };
 
 // Output form of a tracking kernel (template argument).
@@ -193,6 +204,7 @@ struct KernelKey {
 
 // Kernel lookup (defined in pt_kernels.hip).
 const void* track_kernel(const KernelKey& k);
+const void* careful_kernel(const KernelKey& k);        // FP64 keys only
 const void* reset_kernel();
 const void* sort_clear_kernel();
 const void* sort_hist_kernel();
@@ -241,8 +253,9 @@ struct SnapJob {
     int32_t c, i, j, k;
     int32_t g, pid, ks0, cnt;
     int32_t start;        // first pair index of the slot in a flush
+    uint32_t amb;         // FP64: a snapshot of this lane's particle was left undecided (careful pass)
 };
-static_assert(sizeof(SnapJob<double>) == 72 && sizeof(SnapJob<float>) == 56, "SnapJob layout");
+static_assert(sizeof(SnapJob<double>) == 72 && sizeof(SnapJob<float>) == 64, "SnapJob layout");
 
 // Staging of one lane's pathline records (record pass): the bytes of the current 64-byte segment
 // of the particle's record stream and the overflow of the last record (12 doubles), and the

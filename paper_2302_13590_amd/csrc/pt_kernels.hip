@@ -65,6 +65,7 @@ __device__ __forceinline__ double dinf() { return __builtin_huge_val(); }
 // as A -> 0; for x < -1/2 (strong deceleration) the ratio u_e/u_p is formed directly.
 // log1p, log and expm1 are correctly rounded (pt_crmath.h), so every FP64 operation of a
 // step has one defined result.  `amb` counts roundings the accurate phase could not decide.
+template <int CR>
 __device__ __forceinline__ double exit_time64(double u1, double u2, double xi, double& xe,
                                               unsigned& amb) {
     const double A = u2 - u1;
@@ -103,7 +104,7 @@ __device__ __forceinline__ double exit_time64(double u1, double u2, double xi, d
             yl = y.l;
             done = ptcr::log1p_special(x, &L);
         }
-        if (!done) L = ptcr::log_dd_cr(yh, yl, &amb);
+        if (!done) L = ptcr::log_dd_cr<CR>(yh, yl, &amb);
         const double q = L / (ratio ? A : x);
         dt = ratio ? q : r * q;
     }
@@ -113,20 +114,22 @@ __device__ __forceinline__ double exit_time64(double u1, double u2, double xi, d
 
 // Position along one axis after tau: xi + u_p tau expm1(A tau)/(A tau), clamped to [0,1];
 // A = u2 - u1 and u_p = u1 + A xi as the exit selection already formed them.
+template <int CR>
 __device__ __forceinline__ double adv64_au(double A, double up, double xi, double tau, unsigned& amb) {
     if (up == 0.0) return xi;
     const double y = A * tau;
-    const double psi = (y == 0.0) ? 1.0 : ptcr::expm1_cr(y, &amb) / y;
+    const double psi = (y == 0.0) ? 1.0 : ptcr::expm1_cr<CR>(y, &amb) / y;
     double xn = xi + (up * tau) * psi;
     xn = (xn < 0.0) ? 0.0 : xn;
     xn = (xn > 1.0) ? 1.0 : xn;
     return xn;
 }
 
+template <int CR>
 __device__ __forceinline__ double adv64(double u1, double u2, double xi, double tau, unsigned& amb) {
     const double A = u2 - u1;
     const double up = u1 + A * xi;
-    return adv64_au(A, up, xi, tau, amb);
+    return adv64_au<CR>(A, up, xi, tau, amb);
 }
 
 // Earliest exit over the three axes, FP64, with the same result as evaluating exit_time64 on
@@ -144,24 +147,31 @@ constexpr double kFilterMargin = 0x1p-15;
 // exact for x > -1/2, and the quotient stays accurate however small x is), one formula for all
 // lanes; for x <= -1/2 the ratio u_e/u_p is formed directly.  Error: ~7 ulp in x, propagated
 // with a factor below 1, ~10 ulp in the quotient, ~6 ulp in D/u_p: below 1.5e-6 relative, a
-// tenth of what the selection margin allows.  `unsure` is raised when FP32 cannot bound it.
+// tenth of what the selection margin allows.  The bound needs normal FP32 operands and results:
+// `unsure` is raised when u_p, the distance D, the ratio numerator u_e or the estimate itself
+// leaves [2^-100, 2^100] (or the estimate is not finite).  A subnormal distance or estimate
+// carries an absolute rounding of 2^-149, i.e. any relative error, and a zero distance (a
+// particle already on the face, a zero-time crossing) is decided exactly as well.
 __device__ __forceinline__ float exit_estimate(double D, double up, double A, double ue, bool& unsure) {
     const float upf = (float)up;
+    const float Df = (float)D;
     const float rup = __builtin_amdgcn_rcpf(upf);
-    const float rf = (float)D * rup;
+    const float rf = Df * rup;
     const float xf = (float)A * rf;
     const float u = 1.0f + xf;
     const bool ratio = !(xf > -0.5f);
-    const float q = ratio ? (float)ue * rup : u;   // u_e/u_p
+    const float uef = (float)ue;
+    const float q = ratio ? uef * rup : u;   // u_e/u_p
     const float den = ratio ? xf : u - 1.0f;
-    unsure = unsure || !(q >= 0x1p-100f);
+    unsure = unsure || !(q >= 0x1p-100f) || !(fabsf(Df) >= 0x1p-100f) || (ratio && !(fabsf(uef) >= 0x1p-100f));
     const float ph = (u == 1.0f) ? 1.0f   // |x| < 2^-24: log1p(x)/x = 1 - x/2 + ...
                                  : (__builtin_amdgcn_logf(q) * 0.693147181f) * __builtin_amdgcn_rcpf(den);
     const float E = rf * ph;
-    unsure = unsure || !(fabsf(upf) >= 0x1p-100f && fabsf(upf) <= 0x1p100f) || !__builtin_isfinite(E);
+    unsure = unsure || !(fabsf(upf) >= 0x1p-100f && fabsf(upf) <= 0x1p100f) || !(E >= 0x1p-100f && E <= 0x1p120f);
     return E;
 }
 
+template <int CR>
 __device__ __forceinline__ void select_exit64(const double (&u1)[3], const double (&u2)[3],
                                               const double (&xi)[3], double& dt, int32_t& axis,
                                               double& xe, unsigned& amb, double (&Ao)[3],
@@ -211,7 +221,7 @@ __device__ __forceinline__ void select_exit64(const double (&u1)[3], const doubl
     for (int a = 0; a < 3; ++a) unsure = unsure || (a != w && E[a] <= lim);
     if (!unsure) {
         if (w >= 0) {
-            dt = exit_time64(w1, w2, wx, xe, amb);
+            dt = exit_time64<CR>(w1, w2, wx, xe, amb);
             axis = w;
         }
         return;
@@ -219,7 +229,7 @@ __device__ __forceinline__ void select_exit64(const double (&u1)[3], const doubl
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         double e = 0.0;
-        const double ta = exit_time64(u1[a], u2[a], xi[a], e, amb);
+        const double ta = exit_time64<CR>(u1[a], u2[a], xi[a], e, amb);
         if (ta < dt) {
             dt = ta;
             axis = a;
@@ -306,20 +316,20 @@ template <int PREC> struct Real;
 template <> struct Real<P64> { using T = double; };
 template <> struct Real<PMIX> { using T = float; };
 
-template <int PREC>
+template <int PREC, int CR>
 __device__ __forceinline__ double exit_time(typename Real<PREC>::T u1, typename Real<PREC>::T u2,
                                             typename Real<PREC>::T xi, typename Real<PREC>::T& xe,
                                             unsigned& amb) {
-    if constexpr (PREC == P64) return exit_time64(u1, u2, xi, xe, amb);
+    if constexpr (PREC == P64) return exit_time64<CR>(u1, u2, xi, xe, amb);
     else return exit_time_mix(u1, u2, xi, xe, amb);
 }
 
-template <int PREC>
+template <int PREC, int CR>
 __device__ __forceinline__ typename Real<PREC>::T adv(typename Real<PREC>::T u1,
                                                       typename Real<PREC>::T u2,
                                                       typename Real<PREC>::T xi, double tau,
                                                       unsigned& amb) {
-    if constexpr (PREC == P64) return adv64(u1, u2, xi, tau, amb);
+    if constexpr (PREC == P64) return adv64<CR>(u1, u2, xi, tau, amb);
     else return adv_mix(u1, u2, xi, tau, amb);
 }
 
@@ -334,6 +344,7 @@ struct Lane {
     int32_t ks;         // next snapshot index
     unsigned amb;       // undecided roundings of the correctly rounded functions
     unsigned drop;      // pathline records that had no slot
+    unsigned drop0;     // pathline: `drop` when this particle began
     unsigned long long hash;
     double t;
     double s_next;      // time of snapshot ks (+inf past the last)
@@ -480,32 +491,41 @@ __device__ __forceinline__ void cell_xyz(const GridDev& G, int32_t c, int32_t i,
 
 // Position at snapshot time s of a particle whose step started at time t in cell c (i, j, k)
 // with local coordinates x: tau = s - t on every axis.
-template <int PREC, int LAYOUT>
+template <int PREC, int LAYOUT, int CR>
 __device__ __forceinline__ void eval_snap(const GridDev& G, const typename Real<PREC>::T (&u1)[3],
                                           const typename Real<PREC>::T (&u2)[3],
                                           const typename Real<PREC>::T (&x)[3], double t, int32_t c,
                                           int32_t i, int32_t j, int32_t k, double s, double* out,
                                           unsigned& amb) {
     const double tau = s - t;
-    const double a = (double)adv<PREC>(u1[0], u2[0], x[0], tau, amb);
-    const double b = (double)adv<PREC>(u1[1], u2[1], x[1], tau, amb);
-    const double d = (double)adv<PREC>(u1[2], u2[2], x[2], tau, amb);
+    const double a = (double)adv<PREC, CR>(u1[0], u2[0], x[0], tau, amb);
+    const double b = (double)adv<PREC, CR>(u1[1], u2[1], x[1], tau, amb);
+    const double d = (double)adv<PREC, CR>(u1[2], u2[2], x[2], tau, amb);
     cell_xyz<LAYOUT>(G, c, i, j, k, a, b, d, out);
+}
+
+// Snapshot ks of a particle whose step started at (t, x) in cell c.
+template <int PREC, int LAYOUT, int CR>
+__device__ __forceinline__ void snap_at(const GridDev& G, const TrackParams& P,
+                                        const typename Real<PREC>::T (&u1)[3],
+                                        const typename Real<PREC>::T (&u2)[3],
+                                        const typename Real<PREC>::T (&x)[3], double t, int32_t c, int32_t i,
+                                        int32_t j, int32_t k, int64_t pid, int32_t ks, double s, unsigned& amb) {
+    eval_snap<PREC, LAYOUT, CR>(G, u1, u2, x, t, c, i, j, k, s, P.snap_xyz + (pid * P.n_snap + ks) * 3, amb);
 }
 
 // Positions at the snapshot times s with s < to (or s <= to when closed), evaluated from the
 // state at the start of the step with tau = s - t.
-template <int PREC, int LAYOUT>
+template <int PREC, int LAYOUT, int CR>
 __device__ __forceinline__ void write_snaps(Lane<PREC>& L, const GridDev& G,
                                             const typename Real<PREC>::T (&u1)[3],
                                             const typename Real<PREC>::T (&u2)[3],
                                             const TrackParams& P, const double* snap, double to,
                                             bool closed) {
-    double* row = P.snap_xyz + L.pid * (int64_t)P.n_snap * 3;
     while (L.ks < P.n_snap) {
         const double s = L.s_next;
         if (closed ? !(s <= to) : !(s < to)) break;
-        eval_snap<PREC, LAYOUT>(G, u1, u2, L.x, L.t, L.c, L.i, L.j, L.k, s, row + 3 * (int64_t)L.ks, L.amb);
+        snap_at<PREC, LAYOUT, CR>(G, P, u1, u2, L.x, L.t, L.c, L.i, L.j, L.k, L.pid, L.ks, s, L.amb);
         ++L.ks;
         L.s_next = (L.ks < P.n_snap) ? snap[L.ks] : dinf();
     }
@@ -528,7 +548,7 @@ __device__ __forceinline__ void wave_sync() {
 
 // The snapshots of a step ending at `to` (open interval): into the lane's slot when it is free,
 // else evaluated at once.
-template <int PREC, int LAYOUT>
+template <int PREC, int LAYOUT, int CR>
 __device__ __forceinline__ void queue_snaps(Lane<PREC>& L, const GridDev& G,
                                             const typename Real<PREC>::T (&u1)[3],
                                             const typename Real<PREC>::T (&u2)[3], const TrackParams& P,
@@ -555,16 +575,15 @@ __device__ __forceinline__ void queue_snaps(Lane<PREC>& L, const GridDev& G,
         job->ks0 = ks0;
         job->cnt = cnt;
     } else {
-        double* row = P.snap_xyz + L.pid * (int64_t)P.n_snap * 3;
         for (int32_t q = ks0; q < L.ks; ++q)
-            eval_snap<PREC, LAYOUT>(G, u1, u2, L.x, L.t, L.c, L.i, L.j, L.k, snap[q], row + 3 * (int64_t)q, L.amb);
+            snap_at<PREC, LAYOUT, CR>(G, P, u1, u2, L.x, L.t, L.c, L.i, L.j, L.k, L.pid, q, snap[q], L.amb);
     }
 }
 
 // All lanes of the wave: evaluate every pending snapshot of the wave's 64 slots W and free them.
-template <int PREC, int LAYOUT, bool BATCHED>
+template <int PREC, int LAYOUT, bool BATCHED, int CR>
 __device__ __forceinline__ void flush_snaps(SnapJob<typename Real<PREC>::T>* W, const TrackParams& P,
-                                            const double* snap, unsigned& amb) {
+                                            const double* snap) {
     using R = typename Real<PREC>::T;
     const int lane = (int)(threadIdx.x & 63u);
     const int cnt = W[lane].cnt;
@@ -594,8 +613,9 @@ __device__ __forceinline__ void flush_snaps(SnapJob<typename Real<PREC>::T>* W, 
         x[1] = J.x[1];
         x[2] = J.x[2];
         const int32_t ks = J.ks0 + (q - J.start);
-        eval_snap<PREC, LAYOUT>(G, u1, u2, x, J.t, J.c, J.i, J.j, J.k, snap[ks],
-                                P.snap_xyz + ((int64_t)J.pid * P.n_snap + ks) * 3, amb);
+        unsigned a = 0u;
+        snap_at<PREC, LAYOUT, CR>(G, P, u1, u2, x, J.t, J.c, J.i, J.j, J.k, (int64_t)J.pid, ks, snap[ks], a);
+        if (a) W[lo].amb = a;   // the slot's owner hands its particle to the careful pass
     }
     wave_sync();
     W[lane].cnt = 0;
@@ -747,6 +767,7 @@ __device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap
     L.hash = P.hash[p];
     if constexpr (OUT == O_PATH) {
         L.nc0 = L.ncross;
+        L.drop0 = L.drop;
         if (!P.path_count) {
             L.pq = P.path_off[p];
             const int64_t e = P.path_off[p + 1];
@@ -877,7 +898,7 @@ __device__ int32_t quad_transfer(Lane<PREC>& L, const GridDev& G, const TrackPar
 
 // One cell crossing (S1-S7).  Returns 0 to continue, or the final status.  `job`: the lane's
 // slot for deferred snapshots, or null to write them at once.
-template <int PREC, int LAYOUT, int OUT, bool BATCHED>
+template <int PREC, int LAYOUT, int OUT, bool BATCHED, int CR>
 __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& P, const double* snap,
                                               unsigned long long& crossings,
                                               SnapJob<typename Real<PREC>::T>* job = nullptr) {
@@ -902,12 +923,12 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
     R xe = 0;
     double Aa[3], upa[3];   // FP64: gradient and particle velocity of each axis at the step start
     if constexpr (PREC == P64) {
-        select_exit64(u1, u2, L.x, dt, axis, xe, L.amb, Aa, upa);
+        select_exit64<CR>(u1, u2, L.x, dt, axis, xe, L.amb, Aa, upa);
     } else {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             R e = 0;
-            const double ta = exit_time<PREC>(u1[a], u2[a], L.x[a], e, L.amb);
+            const double ta = exit_time<PREC, CR>(u1[a], u2[a], L.x[a], e, L.amb);
             if (ta < dt) {
                 dt = ta;
                 axis = a;
@@ -930,17 +951,17 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
         }
     }
     if (axis < 0 && __builtin_isinf(lim)) {
-        if constexpr (OUT == O_SERIES) write_snaps<PREC, LAYOUT>(L, G, u1, u2, P, snap, dinf(), true);
+        if constexpr (OUT == O_SERIES) write_snaps<PREC, LAYOUT, CR>(L, G, u1, u2, P, snap, dinf(), true);
         return ST_STRANDED;
     }
     const double t_exit = L.t + dt;
     if (t_exit > lim) {
         const double tau = lim - L.t;
-        if constexpr (OUT == O_SERIES) write_snaps<PREC, LAYOUT>(L, G, u1, u2, P, snap, lim, true);
+        if constexpr (OUT == O_SERIES) write_snaps<PREC, LAYOUT, CR>(L, G, u1, u2, P, snap, lim, true);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            if constexpr (PREC == P64) L.x[a] = adv64_au(Aa[a], upa[a], L.x[a], tau, L.amb);
-            else L.x[a] = adv<PREC>(u1[a], u2[a], L.x[a], tau, L.amb);
+            if constexpr (PREC == P64) L.x[a] = adv64_au<CR>(Aa[a], upa[a], L.x[a], tau, L.amb);
+            else L.x[a] = adv<PREC, CR>(u1[a], u2[a], L.x[a], tau, L.amb);
         }
         L.t = lim;
         if constexpr (BATCHED) {
@@ -969,8 +990,8 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
 
     // advance to the exit face: the two other axes move analytically
     if constexpr (OUT == O_SERIES) {
-        if (job) queue_snaps<PREC, LAYOUT>(L, G, u1, u2, P, snap, t_exit, job);
-        else write_snaps<PREC, LAYOUT>(L, G, u1, u2, P, snap, t_exit, false);
+        if (job) queue_snaps<PREC, LAYOUT, CR>(L, G, u1, u2, P, snap, t_exit, job);
+        else write_snaps<PREC, LAYOUT, CR>(L, G, u1, u2, P, snap, t_exit, false);
     }
     {
         const int a1 = (axis == 0) ? 1 : 0;
@@ -986,8 +1007,8 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
             const double Ax = (a1 == 0) ? Aa[0] : Aa[1], ux = (a1 == 0) ? upa[0] : upa[1];
             const double Ay = (a2 == 1) ? Aa[1] : Aa[2], uy = (a2 == 1) ? upa[1] : upa[2];
             (void)v1a, (void)v2a, (void)v1b, (void)v2b;
-            na = adv64_au(Ax, ux, xa, dt, L.amb);
-            nb = adv64_au(Ay, uy, xb, dt, L.amb);
+            na = adv64_au<CR>(Ax, ux, xa, dt, L.amb);
+            nb = adv64_au<CR>(Ay, uy, xb, dt, L.amb);
         } else {
             // the gradient and particle velocity as the exit times formed them
             const float A0 = u2[0] - u1[0], A1 = u2[1] - u1[1], A2 = u2[2] - u1[2];
@@ -1115,12 +1136,47 @@ __device__ __forceinline__ void block_flush(BlockCounters& S, const TrackParams&
     if (threadIdx.x == 0 && S.cross) atomicAdd(&P.counters->crossings, S.cross);
 }
 
+// At the end of a particle in the fast FP64 kernels: if one of its correctly rounded evaluations
+// was left undecided (L.amb != 0; a value within 2^-96 of a rounding midpoint, which the fast
+// kernels do not settle -- that would take registers their loop does not have), hand it to the
+// careful pass instead of finishing it.  Its input state in memory is untouched, so the careful
+// kernel tracks it again from there; this call's crossings of it are taken back and nothing of it
+// is written back.  Returns false (finish it) when there is no free entry; the undecided
+// evaluations are then counted as such.
+template <int PREC, int OUT>
+__device__ __forceinline__ bool hand_off(Lane<PREC>& L, const TrackParams& P, unsigned long long& crossings) {
+    const unsigned long long q = atomicAdd(&P.counters->recheck_tracks, 1ull);
+    const unsigned amb = L.amb;
+    L.amb = 0u;
+    if (q < (unsigned long long)P.recheck_cap) {
+        P.recheck_pid[q] = (int32_t)L.pid;
+        crossings -= (unsigned long long)(L.ncross - P.ncross[L.pid]);
+        if constexpr (OUT == O_PATH) L.drop = L.drop0;
+        return true;
+    }
+    atomicAdd(&P.counters->cr_ambiguous, (unsigned long long)amb);
+    return false;
+}
+
+// Finish a particle of the fast kernels (st > 0), or hand it to the careful pass.
+template <int PREC, int LAYOUT, int OUT, bool BATCHED>
+__device__ __forceinline__ void finish_fast(Lane<PREC>& L, int32_t st, const TrackParams& P, unsigned int* s_hist,
+                                            unsigned long long& crossings) {
+    if constexpr (PREC == P64) {
+        if (L.amb && hand_off<PREC, OUT>(L, P, crossings)) return;
+    }
+    finish<PREC, LAYOUT, OUT, BATCHED>(L, st, P, s_hist);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Waves per SIMD the register allocator is asked to fit.  FP64: four (128 VGPRs, a constant of
 // the rare accurate phase in scratch) instead of three at 136 VGPRs -- the fourth wave hides
 // more of the dependent FP64 latency and the record gathers (C2 -9%, C3 -10%); five (96 VGPRs)
 // spill live loop values and are slower.  Mixed: eight for endpoint runs (C3 -5%), six for
 // timeseries and pathlines (C5 -4%; eight spills there).
+// Rounding mode of the fast kernels: undecided evaluations go to the careful pass.
+constexpr int kFastCr = ptcr::CR_FLAG;
+
 template <int PREC, int OUT>
 constexpr int kWavesStatic = PREC == P64 ? 4 : (OUT == O_END ? 8 : 6);
 // Persistent kernel: FP64 three (168 VGPRs instead of ~175, a few bytes of rarely used values in
@@ -1153,6 +1209,7 @@ k_track_static(TrackParams P) {
         J* jobs = reinterpret_cast<J*>(dyn_lds);
         J* W = jobs + (threadIdx.x & ~63u);
         jobs[threadIdx.x].cnt = 0;
+        jobs[threadIdx.x].amb = 0u;
         wave_sync();
         int32_t st = ST_SKIP;
         if (slot < P.n) {
@@ -1160,21 +1217,22 @@ k_track_static(TrackParams P) {
             st = begin<PREC, LAYOUT, OUT, BATCHED>(L, P, snap);
         }
         for (;;) {
-            if (st == 0) st = track_step<PREC, LAYOUT, OUT, BATCHED>(L, P, snap, crossings, &jobs[threadIdx.x]);
+            if (st == 0) st = track_step<PREC, LAYOUT, OUT, BATCHED, kFastCr>(L, P, snap, crossings, &jobs[threadIdx.x]);
             wave_sync();
             const unsigned long long pend = __ballot(jobs[threadIdx.x].cnt > 0);
             const unsigned long long live = __ballot(st == 0);
             if (pend != 0ull && (__popcll(pend) >= kSnapFlush || live == 0ull))
-                flush_snaps<PREC, LAYOUT, BATCHED>(W, P, snap, L.amb);
+                flush_snaps<PREC, LAYOUT, BATCHED, kFastCr>(W, P, snap);
             if (live == 0ull) break;
         }
-        if (st > 0) finish<PREC, LAYOUT, OUT, BATCHED>(L, st, P, S.hist);
+        L.amb |= jobs[threadIdx.x].amb;   // undecided snapshots evaluated for this lane by the wave
+        if (st > 0) finish_fast<PREC, LAYOUT, OUT, BATCHED>(L, st, P, S.hist, crossings);
     } else {
         if (slot < P.n) {
             L.pid = P.order ? (int64_t)P.order[slot] : slot;
             int32_t st = begin<PREC, LAYOUT, OUT, BATCHED>(L, P, snap);
-            while (st == 0) st = track_step<PREC, LAYOUT, OUT, BATCHED>(L, P, snap, crossings);
-            if (st > 0) finish<PREC, LAYOUT, OUT, BATCHED>(L, st, P, S.hist);
+            while (st == 0) st = track_step<PREC, LAYOUT, OUT, BATCHED, kFastCr>(L, P, snap, crossings);
+            if (st > 0) finish_fast<PREC, LAYOUT, OUT, BATCHED>(L, st, P, S.hist, crossings);
         }
     }
     block_flush(S, P, crossings, L.amb, L.drop);
@@ -1255,13 +1313,37 @@ k_track_persistent(TrackParams P) {
         }
         for (int s = 0; s < steps; ++s) {
             if (L.pid >= 0) {
-                const int32_t st = track_step<PREC, LAYOUT, OUT, BATCHED>(L, P, snap, crossings);
+                const int32_t st = track_step<PREC, LAYOUT, OUT, BATCHED, kFastCr>(L, P, snap, crossings);
                 if (st != 0) {
-                    finish<PREC, LAYOUT, OUT, BATCHED>(L, st, P, S.hist);
+                    finish_fast<PREC, LAYOUT, OUT, BATCHED>(L, st, P, S.hist, crossings);
                     L.pid = -1;
                 }
             }
         }
+    }
+    block_flush(S, P, crossings, L.amb, L.drop);
+}
+
+// Careful pass, FP64: the particles the tracking kernel handed over are tracked again from their
+// input state with every correctly rounded evaluation decided exactly (CR_EXACT), one thread per
+// particle, snapshots and pathline records written again in full.  The list is usually empty; the
+// grid is fixed and strides over it.
+template <int LAYOUT, int OUT, bool BATCHED>
+__global__ void __launch_bounds__(kBlock) k_track_careful(TrackParams P) {
+    __shared__ BlockShared<OUT == O_SERIES> S;
+    const unsigned long long cnt = P.counters->recheck_tracks;
+    const int64_t n = (int64_t)(cnt < (unsigned long long)P.recheck_cap ? cnt : (unsigned long long)P.recheck_cap);
+    if (n == 0) return;   // uniform across the grid: no barrier below is skipped by part of a block
+    const double* snap = block_setup<P64, OUT == O_SERIES>(S, P);
+    unsigned long long crossings = 0;
+    Lane<P64> L;
+    L.amb = 0u;
+    L.drop = 0u;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        L.pid = P.recheck_pid[q];
+        int32_t st = begin<P64, LAYOUT, OUT, BATCHED>(L, P, snap);
+        while (st == 0) st = track_step<P64, LAYOUT, OUT, BATCHED, ptcr::CR_EXACT>(L, P, snap, crossings);
+        if (st > 0) finish<P64, LAYOUT, OUT, BATCHED>(L, st, P, S.hist);
     }
     block_flush(S, P, crossings, L.amb, L.drop);
 }
@@ -1554,6 +1636,29 @@ const void* track_kernel(const KernelKey& k) {
     if (k.precision == PMIX) return pick_out<PMIX, L_CELL>(k);
     if (k.layout == L_FACES) return pick_out<P64, L_FACES>(k);
     return pick_out<P64, L_CELL>(k);
+}
+
+template <int LAYOUT, int OUT>
+const void* pick_careful(const KernelKey& k) {
+    return k.batched ? reinterpret_cast<const void*>(&k_track_careful<LAYOUT, OUT, true>)
+                     : reinterpret_cast<const void*>(&k_track_careful<LAYOUT, OUT, false>);
+}
+
+template <int LAYOUT>
+const void* pick_careful_out(const KernelKey& k) {
+    if (k.out == O_SERIES) return pick_careful<LAYOUT, O_SERIES>(k);
+    if (k.out == O_PATH) return pick_careful<LAYOUT, O_PATH>(k);
+    return pick_careful<LAYOUT, O_END>(k);
+}
+
+const void* careful_kernel(const KernelKey& k) {
+    if (k.layout == L_QUAD) {   // single grid
+        if (k.out == O_SERIES) return reinterpret_cast<const void*>(&k_track_careful<L_QUAD, O_SERIES, false>);
+        if (k.out == O_PATH) return reinterpret_cast<const void*>(&k_track_careful<L_QUAD, O_PATH, false>);
+        return reinterpret_cast<const void*>(&k_track_careful<L_QUAD, O_END, false>);
+    }
+    if (k.layout == L_FACES) return pick_careful_out<L_FACES>(k);
+    return pick_careful_out<L_CELL>(k);
 }
 
 const void* reset_kernel() { return reinterpret_cast<const void*>(&k_reset); }

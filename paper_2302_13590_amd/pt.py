@@ -6,6 +6,7 @@ ImportError when libpt.so has not been built -- there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import dataclasses
 import math
@@ -84,11 +85,12 @@ class pt_summary(ctypes.Structure):
                 ("status_count", ctypes.c_int64 * 8), ("kernel_ms", ctypes.c_double),
                 ("schedule", ctypes.c_int32), ("layout", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("cr_ambiguous", ctypes.c_int64),
-                ("path_records", ctypes.c_int64), ("path_dropped", ctypes.c_int64)]
+                ("path_records", ctypes.c_int64), ("path_dropped", ctypes.c_int64),
+                ("recheck_tracks", ctypes.c_int64)]
 
 
-EXPORTS = ["pt_load_grid", "pt_load_quad_grid", "pt_track", "pt_results", "pt_release", "pt_last_error", "pt_default_opts",
-           "pt_version"]
+EXPORTS = ["pt_load_grid", "pt_load_quad_grid", "pt_track", "pt_results", "pt_release", "pt_shutdown",
+           "pt_last_error", "pt_default_opts", "pt_version"]
 
 _lib = None
 
@@ -118,7 +120,12 @@ def load_library(path: str = LIB_PATH):
     lib.pt_default_opts.restype = None
     lib.pt_version.argtypes = []
     lib.pt_version.restype = ctypes.c_int
+    lib.pt_shutdown.argtypes = []
+    lib.pt_shutdown.restype = ctypes.c_int
     _lib = lib
+    # every graph, event and buffer of the library is released before interpreter and HIP
+    # runtime teardown (atexit handlers run before the C++ static destructors at exit)
+    atexit.register(pt_shutdown)
     return lib
 
 
@@ -226,6 +233,14 @@ def load_any_grid(g, stream=None, balance_tol: float = -1.0) -> Grid:
     return pt_load_grid(g, stream, balance_tol)
 
 
+def pt_shutdown() -> None:
+    """Release every grid, run and cached resource of the library (see pt.h); earlier handles
+    become invalid.  Registered with atexit when the library is loaded."""
+    if _lib is None:
+        return
+    _check(_lib.pt_shutdown())
+
+
 def pt_release(handle) -> None:
     if isinstance(handle, (Grid, Run)):
         h = handle.handle
@@ -321,12 +336,9 @@ def make_opts(mode=PT_ENDPOINT, precision=PT_FP64, schedule=PT_SCHED_AUTO, layou
     return o
 
 
-def pt_track(grids: Sequence[Grid], particles: DeviceParticles, opts: pt_track_opts, stream=None,
-             group_offsets=None, group_grid=None) -> Run:
-    """Enqueue tracking; returns a Run (call pt_results, then pt_release)."""
-    lib = load_library()
+def _particles_arg(grids, particles, group_offsets, group_grid):
     handles = (_p * len(grids))(*[g.handle for g in grids])
-    keep = [handles, opts]
+    keep = [handles]
     pp = pt_particles()
     pp.n = particles.n
     for name in ("cell", "xi", "eta", "zeta", "t", "status", "ncross", "path_hash"):
@@ -338,18 +350,19 @@ def pt_track(grids: Sequence[Grid], particles: DeviceParticles, opts: pt_track_o
         pp.n_groups = gg.shape[0]
         pp.group_offsets = go.ctypes.data
         pp.group_grid = gg.ctypes.data
+    return handles, pp, keep
+
+
+def pt_track(grids: Sequence[Grid], particles: DeviceParticles, opts: pt_track_opts, stream=None,
+             group_offsets=None, group_grid=None) -> Run:
+    """Enqueue tracking; returns a Run (call pt_results, then pt_release)."""
+    lib = load_library()
+    handles, pp, keep = _particles_arg(grids, particles, group_offsets, group_grid)
+    keep.append(opts)
     out = _p()
     _check(lib.pt_track(handles, len(grids), ctypes.byref(pp), ctypes.byref(opts), _stream_ptr(stream),
                         ctypes.byref(out)))
     return Run(out.value, keep)
-
-
-def pt_results(run: Run) -> dict:
-    s = pt_summary()
-    _check(load_library().pt_results(run.handle, ctypes.byref(s)))
-    return dict(crossings=s.crossings, n_tracked=s.n_tracked, status_count=list(s.status_count),
-                kernel_ms=s.kernel_ms, schedule=s.schedule, layout=s.layout, block=s.block, grid=s.grid,
-                cr_ambiguous=s.cr_ambiguous, path_records=s.path_records, path_dropped=s.path_dropped)
 
 
 # --------------------------------------------------------------------------------------------- helper

@@ -70,7 +70,7 @@ def test_path_record_host_dtype_matches_struct():
 
 
 def test_version_and_defaults(lib):
-    assert lib.pt_version() == 102
+    assert lib.pt_version() == 103
     o = pt.pt_default_opts()
     assert (o.mode, o.precision, o.schedule, o.layout) == (0, 0, 0, 0)
     assert o.direction == 1 and o.stop_at_sink == 1 and math.isinf(o.t_max) and o.max_steps == 1 << 20
@@ -198,3 +198,11 @@ def test_missing_library_fails_loudly(tmp_path):
             pt.load_library(str(tmp_path / "absent.so"))
     finally:
         pt._lib = saved
+
+
+def test_shutdown_with_nothing_live(lib):
+    """pt_shutdown holds no device requirement when the library owns nothing: it returns PT_OK
+    and may be called repeatedly (it also runs at interpreter exit)."""
+    assert lib.pt_shutdown() == pt.PT_OK
+    assert lib.pt_shutdown() == pt.PT_OK
+    assert lib.pt_release(None) == pt.PT_OK

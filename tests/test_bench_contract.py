@@ -38,21 +38,40 @@ def test_bench_line():
 
 def test_path_accuracy_report():
     """The mixed-precision accuracy figures of the benchmark line: path agreement counts the
-    particles whose path hash and crossing count both match; travel times are compared only for
-    particles both runs brought to a boundary, relative to the FP64 travel time."""
+    particles whose path hash and crossing count both match; travel times are compared for the
+    particles both runs brought to a boundary face or a sink cell, relative to the FP64 travel
+    time."""
     sys.path.insert(0, ROOT)
     import numpy as np
-    import bench
+    from paper_2302_13590_amd import accuracy as ACC
     n = 8
     ref = {"status": np.array([1, 1, 1, 1, 2, 1, 1, 3], np.int32), "t": np.arange(1.0, 9.0) + 10.0,
            "ncross": np.full(n, 4, np.int32), "path_hash": np.arange(n, dtype=np.uint64)}
     mix = {k: v.copy() for k, v in ref.items()}
     mix["path_hash"][1] += np.uint64(1)          # different path
     mix["ncross"][2] += 1                         # same hash, different count
-    mix["status"][5] = 3                          # did not reach the boundary
+    mix["status"][5] = 3                          # did not terminate
     mix["t"][0] += 1e-3                           # travel time 1 -> 1.001
-    acc = bench.path_accuracy(mix, ref, t0=np.full(n, 10.0))
+    mix["t"][4] += 5e-3                           # sink particle: travel time 5 -> 5.005
+    acc = ACC.path_agreement(mix, ref, t0=np.full(n, 10.0))
     assert acc["particles"] == n and abs(acc["path_agreement"] - 6 / 8) < 1e-12
+    assert abs(acc["status_agreement"] - 7 / 8) < 1e-12
     tr = acc["travel_time_rel_err"]
-    assert tr["particles"] == 5                   # statuses 1 in both: particles 0, 1, 2, 3, 6
+    assert tr["particles"] == 6                   # boundary or sink in both: 0, 1, 2, 3, 4, 6
     assert abs(tr["max"] - 1e-3) < 1e-9 and tr["p50"] == 0.0
+
+
+def test_trajectory_error_report():
+    """Snapshot position error over the entries both runs define, and NaN-pattern agreement."""
+    import numpy as np
+    from paper_2302_13590_amd import accuracy as ACC
+    ref = np.zeros((3, 4, 3))
+    ref[2, 3] = np.nan                            # particle 2 left before the last snapshot
+    mix = ref.copy()
+    mix[0, 1, 0] = 3.0                            # |d| = 5 at one entry
+    mix[0, 1, 1] = 4.0
+    mix[1, 2] = np.nan                            # mixed run left earlier
+    tr = ACC.trajectory_error(mix, ref)
+    assert tr["position_err_m"]["entries"] == 10 and tr["position_err_m"]["max"] == 5.0
+    assert tr["position_err_m"]["p50"] == 0.0
+    assert abs(tr["nan_pattern_agreement"] - 11 / 12) < 1e-6      # reported to 6 digits

@@ -97,3 +97,61 @@ def test_phase_error_bounds(libs, fn):
     assert np.max(e) < 2.0**-68, np.log2(np.max(e))
     Q.quad_relerr(FN[fn], x.ctypes.data, ah.ctypes.data, al.ctypes.data, e.ctypes.data, x.size)
     assert np.max(e) < 2.0**-96, np.log2(np.max(e))
+
+
+def _decimal_series(fn, x):
+    """expm1(x) or log1p(x) for |x| < 2^-40 by its Taylor series in 110-digit decimal."""
+    import decimal
+    ctx = decimal.Context(prec=110)
+    X = decimal.Decimal(x)
+    s, t, k = decimal.Decimal(0), X, 1
+    while True:
+        term = t if fn == "expm1" else ctx.divide(t, k) * (1 if k % 2 else -1)
+        if abs(term) < abs(X) * decimal.Decimal(10) ** -105:
+            return s
+        s = ctx.add(s, term)
+        k += 1
+        t = ctx.divide(ctx.multiply(t, X), k) if fn == "expm1" else ctx.multiply(t, X)
+
+
+def _nearest(v):
+    import decimal
+    import math
+    f = float(v)
+    with decimal.localcontext(decimal.Context(prec=110)):
+        return min((f, float(np.nextafter(f, math.inf)), float(np.nextafter(f, -math.inf))),
+                   key=lambda z: abs(decimal.Decimal(z) - v))
+
+
+@pytest.mark.parametrize("fn", ["expm1", "log1p"])
+def test_small_arguments_near_midpoints(libs, fn):
+    """Arguments 2^-58 .. 2^-42 with regular bit patterns (powers of two, 1.5 and 1.25 times them,
+    moved by up to 40 ulps): there the x^2/2 term lies within 2^-100 of half an ulp of x, so the
+    rounding is decided by the x^3 term or beyond.  Every result must be the double nearest to
+    the 110-digit series value; undecided evaluations are allowed only where that value lies
+    within 2^-140 of a rounding midpoint (relative), and even then the result must be right."""
+    import decimal
+    rng = np.random.Generator(np.random.PCG64(FN[fn] + 300))
+    xs = []
+    for e in range(-58, -41):
+        for base in (2.0 ** e, 1.5 * 2.0 ** e, 1.25 * 2.0 ** e):
+            for k in range(40):
+                xs += [base * (1 - k * 2.0 ** -52), base * (1 + k * 2.0 ** -52)]
+        xs += list(2.0 ** e * rng.uniform(1, 2, 50))
+    x = np.array(xs + [-v for v in xs])
+    S, _ = libs
+    y = np.empty_like(x)
+    amb = S.ptcr_eval(FN[fn], x.ctypes.data, y.ctypes.data, x.size)
+    want = np.empty_like(x)
+    close = 0
+    with decimal.localcontext(decimal.Context(prec=110)):
+        for i, v in enumerate(x):
+            ex = _decimal_series(fn, float(v))
+            want[i] = _nearest(ex)
+            d = decimal.Decimal(want[i])
+            for nb in (np.nextafter(want[i], np.inf), np.nextafter(want[i], -np.inf)):
+                mid = (d + decimal.Decimal(float(nb))) / 2
+                if abs(ex - mid) < abs(ex) * decimal.Decimal(2) ** -140:
+                    close += 1
+    assert np.array_equal(y, want), (fn, x[y != want][:5])
+    assert amb <= close, (fn, amb, close)

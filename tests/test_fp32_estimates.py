@@ -34,20 +34,30 @@ def _log2(v, rng):
     return _perturb(np.log2(v).astype(F), rng)
 
 
-def estimate(D, up, A, ue, rng):
-    """The FP64 kernel's FP32 exit-time estimate, step by step in float32."""
-    upf = up.astype(F)
-    rup = _rcp(upf, rng)
-    rf = (D.astype(F) * rup).astype(F)
-    xf = (A.astype(F) * rf).astype(F)
-    u = (F(1.0) + xf).astype(F)
-    ratio = ~(xf > F(-0.5))
-    q = np.where(ratio, (ue.astype(F) * rup).astype(F), u)
-    den = np.where(ratio, xf, (u - F(1.0)).astype(F))
-    with np.errstate(divide="ignore", invalid="ignore"):
+def estimate(D, up, A, ue, rng, with_unsure=False):
+    """The FP64 kernel's FP32 exit-time estimate, step by step in float32; with ``with_unsure``
+    also the kernel's flag for estimates it cannot bound (operands or result outside
+    [2^-100, 2^100], a zero distance), which sends the selection to the exact evaluation."""
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore", under="ignore"):
+        upf = up.astype(F)
+        Df = D.astype(F)
+        rup = _rcp(upf, rng)
+        rf = (Df * rup).astype(F)
+        xf = (A.astype(F) * rf).astype(F)
+        u = (F(1.0) + xf).astype(F)
+        ratio = ~(xf > F(-0.5))
+        uef = ue.astype(F)
+        q = np.where(ratio, (uef * rup).astype(F), u)
+        den = np.where(ratio, xf, (u - F(1.0)).astype(F))
         lg = (_log2(q, rng) * F(0.693147181)).astype(F)
         ph = np.where(u == F(1.0), F(1.0), (lg * _rcp(den, rng)).astype(F))
-    return (rf * ph).astype(F)
+        E = (rf * ph).astype(F)
+    if not with_unsure:
+        return E
+    lo, hi = F(2.0 ** -100), F(2.0 ** 100)
+    unsure = ~(q >= lo) | ~(np.abs(Df) >= lo) | (ratio & ~(np.abs(uef) >= lo))
+    unsure |= ~((np.abs(upf) >= lo) & (np.abs(upf) <= hi)) | ~((E >= lo) & (E <= F(2.0 ** 120)))
+    return E, unsure
 
 
 def exact_exit(u1, u2, xi):
@@ -138,3 +148,62 @@ def test_kahan_expm1_over_y():
              / y.astype(F)).astype(np.float64)
     tiny = np.abs(y) < 2.0 ** -8
     assert np.abs(naive[tiny] / ref[tiny] - 1.0).max() > 10 * rel[tiny].max()   # the form matters there
+
+
+def _select(E, unsure_axes):
+    """The kernel's candidate choice from three estimates (strict <, lowest axis on ties) and
+    whether it falls back to the exact three-axis evaluation."""
+    w, Ew = -1, np.float32(np.inf)
+    for a in range(3):
+        if E[a] < Ew:
+            w, Ew = a, E[a]
+    lim = np.float32(Ew * np.float32(1.0 + MARGIN))
+    near = any(a != w and E[a] <= lim for a in range(3))
+    return w, bool(near or any(unsure_axes))
+
+
+def test_subnormal_estimates_fall_back_to_exact():
+    """Exit times in the FP32 subnormal range: the estimates' rounding (2^-149 absolute) can
+    reverse the order of two axes, so the kernel must not trust them.  A particle 1.2542e-43
+    from its exit face on axis 0 (u = -0.125) and 1.00515e-42 on axis 1 (u = -1): the exact
+    times are 1.00336e-42 and 1.00515e-42 (axis 0 first), the FP32 estimates order them the
+    other way and no axis lies within the 2^-15 margin of the candidate -- only the unsure
+    flag keeps the choice exact."""
+    rng = np.random.default_rng(3)
+    xi = np.array([1.2542e-43, 1.00515e-42, 0.5])
+    u = np.array([-0.125, -1.0, 0.0])
+    t = np.array([xi[0] / 0.125, xi[1] / 1.0, np.inf])
+    assert t[0] < t[1]
+    D = -xi[:2]
+    E, uns = estimate(D, u[:2], np.zeros(2), u[:2], rng, with_unsure=True)
+    E = np.array([E[0], E[1], np.float32(np.inf)])
+    w_old, fallback_old = _select(E, [False, False, False])
+    assert w_old == 1 and not fallback_old          # the unguarded rule would take axis 1
+    w, fallback = _select(E, list(uns) + [False])
+    assert fallback                                 # the guarded rule evaluates every axis exactly
+
+
+def test_estimate_bounded_whenever_trusted():
+    """Over distances down to the FP64 subnormal range and velocities over +-120 decades, every
+    estimate the kernel trusts (unsure not raised) is within the claimed bound; every other one
+    is decided by the exact evaluation."""
+    rng = np.random.default_rng(99)
+    worst, trusted, total = 0.0, 0, 0
+    for _ in range(6):
+        n = 200_000
+        mag = 10.0 ** rng.uniform(-40, 40, n)
+        u1 = mag * rng.uniform(0.1, 1.0, n) * np.where(rng.random(n) < 0.5, 1.0, -1.0)
+        u2 = u1 * 10.0 ** rng.uniform(-6, 6, n)
+        xi = np.where(rng.random(n) < 0.5, rng.random(n), 10.0 ** rng.uniform(-320, 0, n))
+        xi = np.where(rng.random(n) < 0.5, xi, 1.0 - xi)
+        A, up, ue, D, x, t = exact_exit(u1, u2, xi)
+        ok = (ue * up > 0) & np.isfinite(t) & (t > 0)
+        E, uns = estimate(D[ok], up[ok], A[ok], ue[ok], rng, with_unsure=True)
+        keep = ~uns
+        rel = np.abs(E[keep].astype(np.float64) / t[ok][keep] - 1.0)
+        trusted += int(keep.sum())
+        total += int(ok.sum())
+        if rel.size:
+            worst = max(worst, float(rel.max()))
+    assert trusted > total // 4 and trusted < total     # both outcomes occur in this range
+    assert worst < BOUND, worst

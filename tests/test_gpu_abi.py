@@ -128,3 +128,26 @@ def test_graph_replays_match_eager(pt):
                 assert np.array_equal(res[k], eager[0][k], equal_nan=True), (sched, rep, k)
     del noise
     h.release()
+
+
+def test_shutdown_releases_everything_and_library_restarts(pt):
+    """pt_shutdown releases live grids, live runs and the pooled runs (with their graphs); every
+    earlier handle is then invalid, and the library works again afterwards."""
+    lib = pt.load_library()
+    g = C.c1().grids[0]
+    h = pt.pt_load_grid(g)
+    dp = pt.DeviceParticles.from_numpy(C.c1(n=300).particles)
+    pooled = pt.pt_track([h], dp, pt.make_opts(use_graph=1))
+    pt.pt_results(pooled)
+    pooled.release()                                          # goes to the pool, graph cached
+    live = pt.pt_track([h], dp.clone(), pt.make_opts())       # never released by the caller
+    raw_grid, raw_run = h.handle, live.handle
+    assert lib.pt_shutdown() == pt.PT_OK
+    assert lib.pt_release(ctypes.c_void_p(raw_run)) == -2
+    assert lib.pt_release(ctypes.c_void_p(raw_grid)) == -2
+    h.handle = None
+    live.handle = None
+    p = C.c1(n=300).particles
+    r = O.track(g, p)
+    out = gpu_track([g], p, use_graph=1)
+    compare(out, r, label="after shutdown", spacing=(10.0, 10.0, 10.0))

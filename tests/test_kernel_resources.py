@@ -71,7 +71,9 @@ def _waves_floor(name):
 
 
 def test_tracking_kernel_occupancy(usage):
-    occ = {k: v.get("Occupancy", 0) for k, v in usage.items() if "k_track_" in k}
+    # the careful pass (k_track_careful) runs only for the rare particles handed to it and has no
+    # occupancy target
+    occ = {k: v.get("Occupancy", 0) for k, v in usage.items() if re.search(r"k_track_(static|persistent)", k)}
     assert len(occ) >= 30, sorted(occ)
     low = {k: o for k, o in occ.items() if o < _waves_floor(k)}
     assert not low, low
