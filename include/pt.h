@@ -291,8 +291,8 @@ typedef struct {
                                    * inputs: arguments near 2^-53 .. 2^-50 with regular bit      *
                                    * patterns); each was tracked again from its input state by a *
                                    * careful pass that decides such arguments exactly.  Beyond   *
-                                   * 2^20 per call the rest keep their first results and count  *
-                                   * in cr_ambiguous.                                            */
+                                   * 2^20 per call (2^18 for pt_track_noalloc) the rest keep     *
+                                   * their first results and count in cr_ambiguous.              */
 } pt_summary;
 
 /* Wait for the run, then fill *out.  Reports asynchronous device errors of
@@ -302,6 +302,46 @@ int pt_results(pt_run* run, pt_summary* out);
 /* Release a pt_grid* or pt_run* (waits for a run still in flight).  NULL is a
  * no-op.  A pointer that is not a live handle gives PT_ERR_BAD_HANDLE. */
 int pt_release(void* handle);
+
+/* ---- allocation-free tracking ----------------------------------------------------------- */
+/*
+ * For callers that cannot allocate memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  pt_track_noalloc enqueues the same kernels as pt_track,
+ * with the same arguments, validation and results, but calls no hipMalloc, hipFree or other
+ * allocating routine, host or device, and creates no run handle, event or graph.  Its scratch
+ * (the counter block, the per-call tables, the ordering buffers, the pathline offset scan's
+ * tile sums and the careful pass's particle list) is one array of PT_NOALLOC_SCRATCH_BYTES in the library's device code, one copy
+ * per GPU, held until the process ends.  Limits (PT_ERR_UNSUPPORTED beyond them): the tables of
+ * one call -- a 160-byte view per grid for batched or transient runs, the group table, the
+ * snapshot times, the time-step ends -- at most 64 KiB; a pathline count pass at most 2^26
+ * particles; ordering by starting cell (PT_SORT_CELL) only while 12 bytes per particle plus
+ * 4 bytes per cell fit in the remaining ~30.9 MiB (PT_SORT_AUTO then simply does not order).
+ *
+ * The run's counts are written, once its kernels have run, to `counts` (device memory owned by
+ * the caller, PT_COUNTS_WORDS int64): PT_COUNT_CROSSINGS, PT_COUNT_TRACKED,
+ * PT_COUNT_STATUS + s for each status s, PT_COUNT_CR_AMBIGUOUS, PT_COUNT_PATH_RECORDS,
+ * PT_COUNT_PATH_DROPPED, PT_COUNT_RECHECK_TRACKS (the fields of pt_summary, see there), the
+ * remaining words 0.
+ * Synchronise `hip_stream` before reading them or the particle outputs.  use_graph is ignored
+ * (the kernels are launched directly; a capturing caller records them).
+ *
+ * Every call on one GPU uses that GPU's single scratch array, which keeps the last call's
+ * contents: calls whose work overlaps on one GPU (other streams or threads, before the previous
+ * call's kernels finished) race and give wrong results.  Calls on one stream are ordered and safe.
+ * The call clears what must start at zero (counters, ordering histogram) with kernels, not
+ * memsets.  Errors: as pt_track; PT_ERR_INVALID_ARG for counts == NULL.
+ */
+#define PT_NOALLOC_SCRATCH_BYTES (32 << 20)
+#define PT_COUNTS_WORDS 16
+#define PT_COUNT_CROSSINGS 0
+#define PT_COUNT_TRACKED 1
+#define PT_COUNT_STATUS 2
+#define PT_COUNT_CR_AMBIGUOUS 10
+#define PT_COUNT_PATH_RECORDS 11
+#define PT_COUNT_PATH_DROPPED 12
+#define PT_COUNT_RECHECK_TRACKS 13
+int pt_track_noalloc(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p,
+                     const pt_track_opts* o, void* hip_stream, int64_t* counts);
 
 /* Release everything the library holds: every live grid and run handle (waiting for the
  * devices they use first) and the released runs kept for reuse, with their cached hipGraphs,

@@ -18,6 +18,10 @@
 
 using namespace pt;
 
+// Scratch of the allocation-free entry point (pt_track_noalloc), one copy per device.  Host code
+// never uses this name as an address: it takes the array's device address once per device with
+// hipGetSymbolAddress (scratch_of below).
+static __device__ __align__(256) unsigned char scratch[PT_NOALLOC_SCRATCH_BYTES];
 
 static_assert(sizeof(pt_path_record) == sizeof(PathRec) && offsetof(pt_path_record, cell) == offsetof(PathRec, cell) &&
                   offsetof(pt_path_record, face) == offsetof(PathRec, face) && offsetof(pt_path_record, z) == offsetof(PathRec, z),
@@ -312,9 +316,9 @@ hipError_t launch(const void* fn, dim3 grid, dim3 block, void* arg, size_t lds, 
 
 
 // ---------------------------------------------------------------------------------------------
-// A tracking call in steps: the argument checks, the launch plan (kernel, shape, table and
-// ordering-buffer layout), the binding of the kernel arguments to device buffers and the launch
-// sequence.
+// pt_track and pt_track_noalloc share the argument checks, the launch plan (kernel, shape,
+// table and ordering-buffer layout), the binding of the kernel arguments to device buffers and
+// the launch sequence; they differ in where those buffers come from.
 
 // Checks every argument of a tracking call (no device work); *dev and *n_cu describe the
 // current device.
@@ -701,6 +705,73 @@ void build_seq(const Plan& PL, int64_t n, Counters** cptr, TrackParams* P, SortP
         if (SC->ntiles > 1) seq.push(scan_add_kernel(), dim3((unsigned)SC->ntiles), dim3(kScanBlock), SC, sizeof *SC);
     }
 }
+
+// ---------------------------------------------------------------------------------------------
+// Scratch of the allocation-free entry point: one array per device, in the library's code
+// object, holding the counter block, the per-call tables, the ordering buffers and the
+// pathline scan's tile sums of one call at a time.  Its device address is taken once per
+// device (hipGetSymbolAddress, with that device current) and used for every access from the
+// host: the array's own name is only a host-side stand-in.
+constexpr size_t kScratchBytes = (size_t)PT_NOALLOC_SCRATCH_BYTES;
+constexpr size_t kScratchCounters = 0;                       // Counters (256 B)
+constexpr size_t kScratchTables = 256;                       // per-call tables, up to kScratchTablesMax
+constexpr size_t kScratchTablesMax = (size_t)64 << 10;
+constexpr size_t kScratchScan = kScratchTables + kScratchTablesMax;   // pathline tile sums
+constexpr size_t kScratchScanMax = (size_t)64 << 10;
+constexpr size_t kScratchRecheck = kScratchScan + kScratchScanMax;    // careful pass particle list
+constexpr int64_t kScratchRecheckTracks = (int64_t)1 << 18;           //   (1 MiB)
+constexpr size_t kScratchRecheckMax = sizeof(int32_t) * kScratchRecheckTracks;
+constexpr size_t kScratchSort = kScratchRecheck + kScratchRecheckMax; // ordering buffers: the rest
+static_assert(sizeof(Counters) <= kScratchTables, "counter block fits its scratch slot");
+static_assert(kScratchSort < kScratchBytes, "scratch layout");
+
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (taken on the first call on the device).
+int scratch_of(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(PT_ERR_UNSUPPORTED, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(hip_code(e), "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return PT_OK;
+}
+
+// Writes the per-call tables into device memory through small fill kernels whose arguments
+// carry the bytes: no staging buffer and no copy from host memory that could still be in use.
+struct TableFill {
+    unsigned char* dst;   // device table region
+    FillArgs A;
+    hipStream_t s;
+    hipError_t err = hipSuccess;
+    void flush() {
+        if (A.nbytes && err == hipSuccess) err = launch(fill_kernel(), dim3(1), dim3(256), &A, 0, s);
+        A.nbytes = 0;
+    }
+    void put(size_t off, const void* src, size_t bytes) {
+        const unsigned char* b = static_cast<const unsigned char*>(src);
+        while (bytes) {
+            if (A.nbytes && (A.dst + A.nbytes != dst + off || A.nbytes == sizeof A.bytes)) flush();
+            if (!A.nbytes) A.dst = dst + off;
+            const size_t take = std::min(bytes, sizeof A.bytes - (size_t)A.nbytes);
+            std::memcpy(A.bytes + A.nbytes, b, take);
+            A.nbytes += (uint32_t)take;
+            b += take;
+            off += take;
+            bytes -= take;
+        }
+    }
+};
 
 }  // namespace
 
@@ -1093,6 +1164,55 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
     r->launched = true;
     add_live(r);
     *out = r;
+    return PT_OK;
+}
+
+int pt_track_noalloc(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p,
+                     const pt_track_opts* o, void* hip_stream, int64_t* counts) {
+    g_err.clear();
+    if (!counts) return fail(PT_ERR_INVALID_ARG, "counts must not be NULL");
+    int dev = 0, n_cu = 0;
+    int rc = check_track_args(grids, n_grids, p, o, &dev, &n_cu);
+    if (rc != PT_OK) return rc;
+    Plan PL;
+    rc = make_plan(grids, n_grids, p, o, n_cu, kScratchBytes - kScratchSort, kScratchRecheckTracks, &PL);
+    if (rc != PT_OK) return rc;
+    if (PL.tables > kScratchTablesMax)
+        return fail(PT_ERR_UNSUPPORTED, "the call's tables (grid views, groups, snapshot times, time steps) take %zu "
+                    "bytes, above the %zu of the allocation-free scratch", PL.tables, kScratchTablesMax);
+    if (PL.scan_bytes > kScratchScanMax)
+        return fail(PT_ERR_UNSUPPORTED, "a pathline count pass over %lld particles needs %zu bytes of scan "
+                    "scratch, above the %zu available", (long long)p->n, PL.scan_bytes, kScratchScanMax);
+    unsigned char* base = nullptr;
+    rc = scratch_of(dev, &base);
+    if (rc != PT_OK) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    Counters* cptr = reinterpret_cast<Counters*>(base + kScratchCounters);
+    TrackParams P;
+    SortParams SP;
+    ScanParams SC;
+    bind_params(PL, grids, n_grids, p, o, base + kScratchTables, base + kScratchSort,
+                reinterpret_cast<int64_t*>(base + kScratchScan), base + kScratchRecheck, cptr, P, SP, SC);
+    TableFill tf;
+    tf.dst = base + kScratchTables;
+    tf.A.nbytes = 0;
+    tf.s = s;
+    write_tables(PL, grids, n_grids, p, o, [&](size_t off, const void* src, size_t bytes) { tf.put(off, src, bytes); });
+    tf.flush();
+    hipError_t e = tf.err;
+    LaunchSeq seq;
+    build_seq(PL, p->n, &cptr, &P, &SP, &SC, seq);
+    CountsParams CP;
+    CP.c = cptr;
+    CP.out = counts;
+    CP.path_pass = PL.path ? (PL.path_count ? 1 : 2) : 0;
+    seq.push(counts_kernel(), dim3(1), dim3(64), &CP, sizeof CP);
+    for (int q = 0; e == hipSuccess && q < seq.n; ++q)
+        e = launch(seq.v[q].fn, seq.v[q].grid, seq.v[q].block, seq.v[q].arg, seq.v[q].lds, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(hip_code(e), "launch failed: %s", hipGetErrorString(e));
+    }
     return PT_OK;
 }
 

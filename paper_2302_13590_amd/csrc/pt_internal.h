@@ -241,6 +241,24 @@ struct BuildQuadParams {
     int* err;                   // [4]: non-finite flow, bad porosity, bad flags, unbalanced
 };
 
+// Allocation-free entry point (pt_track_noalloc).  Its per-call tables are written by small
+// fill kernels whose argument carries the bytes (no staging buffer, nothing read from host
+// memory after the call returns), and its counter block is copied into the caller's counts.
+struct FillArgs {
+    unsigned char* dst;
+    uint32_t nbytes;
+    uint32_t pad;
+    unsigned char bytes[2048];
+};
+struct CountsParams {
+    const Counters* c;
+    int64_t* out;          // PT_COUNTS_WORDS int64, device
+    int32_t path_pass;     // 0: none, 1: count pass, 2: record pass
+    int32_t pad;
+};
+const void* fill_kernel();
+const void* counts_kernel();
+
 constexpr int kMaxSnapLds = 1024;
 
 // Slot of one lane for deferred snapshots (static kernel, timeseries, packed layouts): the

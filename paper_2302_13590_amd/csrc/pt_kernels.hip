@@ -1348,6 +1348,32 @@ __global__ void __launch_bounds__(kBlock) k_track_careful(TrackParams P) {
     block_flush(S, P, crossings, L.amb, L.drop);
 }
 
+// Allocation-free entry point: write the argument's bytes to dst.
+__global__ void __launch_bounds__(256) k_fill(FillArgs A) {
+    for (uint32_t q = threadIdx.x; q < A.nbytes; q += blockDim.x) A.dst[q] = A.bytes[q];
+}
+
+// Allocation-free entry point: the run's counters as the caller's counts (the fields of
+// pt_summary that the device computes, in the order PT_COUNT_* of pt.h).
+__global__ void k_counts(CountsParams C) {
+    if (threadIdx.x != 0) return;
+    const Counters& c = *C.c;
+    int64_t tracked = 0;
+    for (int q = 0; q < 8; ++q) {
+        C.out[2 + q] = (int64_t)c.status[q];
+        tracked += (int64_t)c.status[q];
+    }
+    C.out[0] = (int64_t)c.crossings;
+    C.out[1] = tracked;
+    C.out[10] = (int64_t)c.cr_ambiguous;
+    C.out[11] = C.path_pass == 1 ? (int64_t)c.crossings
+                                 : (C.path_pass == 2 ? (int64_t)c.crossings - (int64_t)c.path_dropped : 0);
+    C.out[12] = C.path_pass == 2 ? (int64_t)c.path_dropped : 0;
+    C.out[13] = (int64_t)c.recheck_tracks;
+    C.out[14] = 0;
+    C.out[15] = 0;
+}
+
 __global__ void k_reset(Counters* c) {
     unsigned long long* w = reinterpret_cast<unsigned long long*>(c);
     const int n = sizeof(Counters) / sizeof(unsigned long long);
@@ -1662,6 +1688,8 @@ const void* careful_kernel(const KernelKey& k) {
 }
 
 const void* reset_kernel() { return reinterpret_cast<const void*>(&k_reset); }
+const void* fill_kernel() { return reinterpret_cast<const void*>(&k_fill); }
+const void* counts_kernel() { return reinterpret_cast<const void*>(&k_counts); }
 const void* sort_clear_kernel() { return reinterpret_cast<const void*>(&k_sort_clear); }
 const void* sort_hist_kernel() { return reinterpret_cast<const void*>(&k_sort_hist); }
 const void* sort_scan_tiles_kernel() { return reinterpret_cast<const void*>(&k_sort_scan_tiles); }

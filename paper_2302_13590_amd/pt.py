@@ -89,8 +89,14 @@ class pt_summary(ctypes.Structure):
                 ("recheck_tracks", ctypes.c_int64)]
 
 
-EXPORTS = ["pt_load_grid", "pt_load_quad_grid", "pt_track", "pt_results", "pt_release", "pt_shutdown",
-           "pt_last_error", "pt_default_opts", "pt_version"]
+EXPORTS = ["pt_load_grid", "pt_load_quad_grid", "pt_track", "pt_track_noalloc", "pt_results", "pt_release",
+           "pt_shutdown", "pt_last_error", "pt_default_opts", "pt_version"]
+# pt_track_noalloc: its counts array (int64 words) and their meaning
+PT_NOALLOC_SCRATCH_BYTES = 32 << 20
+PT_COUNTS_WORDS = 16
+PT_COUNT_CROSSINGS, PT_COUNT_TRACKED, PT_COUNT_STATUS = 0, 1, 2
+PT_COUNT_CR_AMBIGUOUS, PT_COUNT_PATH_RECORDS, PT_COUNT_PATH_DROPPED = 10, 11, 12
+PT_COUNT_RECHECK_TRACKS = 13
 
 _lib = None
 
@@ -110,6 +116,9 @@ def load_library(path: str = LIB_PATH):
     lib.pt_track.argtypes = [ctypes.POINTER(_p), ctypes.c_int32, ctypes.POINTER(pt_particles),
                              ctypes.POINTER(pt_track_opts), _p, ctypes.POINTER(_p)]
     lib.pt_track.restype = ctypes.c_int
+    lib.pt_track_noalloc.argtypes = [ctypes.POINTER(_p), ctypes.c_int32, ctypes.POINTER(pt_particles),
+                                     ctypes.POINTER(pt_track_opts), _p, _p]
+    lib.pt_track_noalloc.restype = ctypes.c_int
     lib.pt_results.argtypes = [_p, ctypes.POINTER(pt_summary)]
     lib.pt_results.restype = ctypes.c_int
     lib.pt_release.argtypes = [_p]
@@ -363,6 +372,35 @@ def pt_track(grids: Sequence[Grid], particles: DeviceParticles, opts: pt_track_o
     _check(lib.pt_track(handles, len(grids), ctypes.byref(pp), ctypes.byref(opts), _stream_ptr(stream),
                         ctypes.byref(out)))
     return Run(out.value, keep)
+
+
+def pt_track_noalloc(grids: Sequence[Grid], particles: DeviceParticles, opts: pt_track_opts,
+                     counts: torch.Tensor, stream=None, group_offsets=None, group_grid=None) -> None:
+    """Enqueue tracking with the library's per-device scratch (nothing is allocated); the run's
+    counts go to `counts`, a device int64 tensor of PT_COUNTS_WORDS, once the stream reaches them."""
+    assert counts.dtype == torch.int64 and counts.numel() >= PT_COUNTS_WORDS and counts.is_contiguous()
+    lib = load_library()
+    handles, pp, keep = _particles_arg(grids, particles, group_offsets, group_grid)
+    _check(lib.pt_track_noalloc(handles, len(grids), ctypes.byref(pp), ctypes.byref(opts), _stream_ptr(stream),
+                                counts.data_ptr()))
+
+
+def counts_summary(counts) -> dict:
+    """The fields of a pt_track_noalloc counts array (host copy) as in pt_results' summary."""
+    c = [int(v) for v in (counts.cpu().tolist() if isinstance(counts, torch.Tensor) else counts)]
+    return dict(crossings=c[PT_COUNT_CROSSINGS], n_tracked=c[PT_COUNT_TRACKED],
+                status_count=c[PT_COUNT_STATUS:PT_COUNT_STATUS + 8], cr_ambiguous=c[PT_COUNT_CR_AMBIGUOUS],
+                path_records=c[PT_COUNT_PATH_RECORDS], path_dropped=c[PT_COUNT_PATH_DROPPED],
+                recheck_tracks=c[PT_COUNT_RECHECK_TRACKS])
+
+
+def pt_results(run: Run) -> dict:
+    s = pt_summary()
+    _check(load_library().pt_results(run.handle, ctypes.byref(s)))
+    return dict(crossings=s.crossings, n_tracked=s.n_tracked, status_count=list(s.status_count),
+                kernel_ms=s.kernel_ms, schedule=s.schedule, layout=s.layout, block=s.block, grid=s.grid,
+                cr_ambiguous=s.cr_ambiguous, path_records=s.path_records, path_dropped=s.path_dropped,
+                recheck_tracks=s.recheck_tracks)
 
 
 # --------------------------------------------------------------------------------------------- helper
