@@ -67,7 +67,7 @@ int main(void) {
         eta[3] = __builtin_nan("");
         t[4] = __builtin_inf();
         xi[6] = 1.0;             /* on a face */
-        oracle_opts o = {rep % 2 ? -1 : 1, rep % 3 ? 60.0 : __builtin_inf(), rep == 2 ? 3 : 1 << 20, rep % 2,
+        oracle_opts o = {rep % 2 ? -1 : 1, rep % 3 ? 60.0 : __builtin_inf(), rep == 2 ? 3 : 2000, rep % 2,
                          snaps, n_snap, snap_xyz, out_xyz, cap, pc, pf, pt, px, rep % 2 ? 2 : 1};
         if (oracle_track(&g, &o, n, cell, xi, eta, zeta, t, status, ncross, hash) != 0) return 2;
         const double ends[3] = {4.0, 30.0, __builtin_inf()};
