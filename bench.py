@@ -494,7 +494,7 @@ def main():
                     wname, acc["path_agreement"], acc["travel_time_rel_err"]["p50"], acc["travel_time_rel_err"]["p99"]))
             variants[tag] = v
             log("variant %s: %.4g crossings/s, kernel %.3f ms" % (tag, r["value"], r["kernel_ms"]))
-        if mode == "endpoint" and wname == "C2":
+        if mode == "endpoint" and wname == "C2" and not args.only:
             r = case.time_pathline("fp64", sched, args.steps, args.warmup, **params)
             variants["C2_fp64_pathline"] = dict(
                 value=r["value"], ms_per_step=round(r["ms_per_step"], 4), count_ms=round(r["count_ms"], 4),

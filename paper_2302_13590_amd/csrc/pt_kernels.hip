@@ -34,6 +34,8 @@
 // step and the lane's index is its current step).
 #include <math.h>
 
+#include <type_traits>
+
 #include "pt_crmath.h"
 #include "pt_internal.h"
 
@@ -163,11 +165,13 @@ __device__ __forceinline__ float exit_estimate(double D, double up, double A, do
     const float uef = (float)ue;
     const float q = ratio ? uef * rup : u;   // u_e/u_p
     const float den = ratio ? xf : u - 1.0f;
-    unsure = unsure || !(q >= 0x1p-100f) || !(fabsf(Df) >= 0x1p-100f) || (ratio && !(fabsf(uef) >= 0x1p-100f));
     const float ph = (u == 1.0f) ? 1.0f   // |x| < 2^-24: log1p(x)/x = 1 - x/2 + ...
                                  : (__builtin_amdgcn_logf(q) * 0.693147181f) * __builtin_amdgcn_rcpf(den);
     const float E = rf * ph;
-    unsure = unsure || !(fabsf(upf) >= 0x1p-100f && fabsf(upf) <= 0x1p100f) || !(E >= 0x1p-100f && E <= 0x1p120f);
+    // one range test for the operands (none can be NaN here: a NaN q needs a zero distance, which
+    // the test catches), NaN-safe comparisons for the estimate
+    const float lo = fminf(fminf(fabsf(Df), fabsf(upf)), fminf(q, ratio ? fabsf(uef) : 1.0f));
+    unsure = unsure || !(lo >= 0x1p-100f) || !(fabsf(upf) <= 0x1p100f) || !(E >= 0x1p-100f && E <= 0x1p120f);
     return E;
 }
 
@@ -249,15 +253,21 @@ constexpr float kNearZero = 0x1p-10f;
 constexpr float kLn2f = 0.693147181f;
 constexpr float kLog2ef = 1.44269504f;
 
-__device__ __forceinline__ double exit_time_mix(float u1, float u2, float xi, float& xe, unsigned& amb) {
+// Local coordinates of the mixed kernels: FP32, or FP64 (kMixedCoord64) -- then the distance to
+// the face is formed in FP64 before it is rounded to FP32, and advances are added in FP64.
+constexpr bool kMixedCoord64 = false;
+using MixCoord = std::conditional_t<kMixedCoord64, double, float>;
+
+__device__ __forceinline__ double exit_time_mix(float u1, float u2, MixCoord xc, float& xe, unsigned& amb) {
     (void)amb;
+    const float xi = (float)xc;
     const float A = u2 - u1;
     const float up = fmaf(A, xi, u1);
     const bool pos = up > 0.0f;
     xe = pos ? 1.0f : 0.0f;
     const float ue = pos ? u2 : u1;
     if (!((pos && ue > 0.0f) | (up < 0.0f && ue < 0.0f))) return dinf();
-    const float D = xe - xi;
+    const float D = (float)((MixCoord)xe - xc);
     const float rup = __builtin_amdgcn_rcpf(up);
     const float r = D * rup;
     const float x = A * r;
@@ -283,52 +293,57 @@ __device__ __forceinline__ double exit_time_mix(float u1, float u2, float xi, fl
     return (double)dt;
 }
 
-__device__ __forceinline__ float adv_mix_au(float A, float up, float xi, double tau) {
+__device__ __forceinline__ MixCoord adv_mix_au(float A, float up, MixCoord xi, double tau) {
     if (up == 0.0f) return xi;
     const float tf = (float)tau;
     const float y = A * tf;
-    float xn;
+    MixCoord xn;
     if (fabsf(y) < kNearZero) {
         // expm1(y)/y = 1 + y/2 + y^2/6 + y^3/24 + y^4/120 + ..., truncation below 2^-59 here
         const double yd = (double)A * tau;
         const double psi = fma(yd, fma(yd, fma(yd, fma(yd, 1.0 / 120.0, 1.0 / 24.0), 1.0 / 6.0), 0.5), 1.0);
-        xn = (float)fma((double)up * tau, psi, (double)xi);
+        xn = (MixCoord)fma((double)up * tau, psi, (double)xi);
     } else {
         // v - 1 is exact for |y| < 1/8 (Sterbenz) and not zero here; beyond, (v - 1)/y
         const float v = __builtin_amdgcn_exp2f(y * kLog2ef);
         const float den = (fabsf(y) < 0.125f) ? __builtin_amdgcn_logf(v) * kLn2f : y;
         const float ps = (v - 1.0f) * __builtin_amdgcn_rcpf(den);
-        xn = fmaf(up * tf, ps, xi);
+        if constexpr (kMixedCoord64) xn = xi + (double)((up * tf) * ps);
+        else xn = fmaf(up * tf, ps, xi);
     }
-    xn = (xn < 0.0f) ? 0.0f : xn;
-    xn = (xn > 1.0f) ? 1.0f : xn;
+    xn = (xn < (MixCoord)0) ? (MixCoord)0 : xn;
+    xn = (xn > (MixCoord)1) ? (MixCoord)1 : xn;
     return xn;
 }
 
-__device__ __forceinline__ float adv_mix(float u1, float u2, float xi, double tau, unsigned& amb) {
+__device__ __forceinline__ MixCoord adv_mix(float u1, float u2, MixCoord xi, double tau, unsigned& amb) {
     (void)amb;
     const float A = u2 - u1;
-    return adv_mix_au(A, fmaf(A, xi, u1), xi, tau);
+    return adv_mix_au(A, fmaf(A, (float)xi, u1), xi, tau);
 }
 
 // ---------------------------------------------------------------------------------------------
 template <int PREC> struct Real;
 template <> struct Real<P64> { using T = double; };
 template <> struct Real<PMIX> { using T = float; };
+// Type of the local coordinates of a lane.
+template <int PREC> struct Coord;
+template <> struct Coord<P64> { using T = double; };
+template <> struct Coord<PMIX> { using T = MixCoord; };
 
 template <int PREC, int CR>
 __device__ __forceinline__ double exit_time(typename Real<PREC>::T u1, typename Real<PREC>::T u2,
-                                            typename Real<PREC>::T xi, typename Real<PREC>::T& xe,
+                                            typename Coord<PREC>::T xi, typename Real<PREC>::T& xe,
                                             unsigned& amb) {
     if constexpr (PREC == P64) return exit_time64<CR>(u1, u2, xi, xe, amb);
     else return exit_time_mix(u1, u2, xi, xe, amb);
 }
 
 template <int PREC, int CR>
-__device__ __forceinline__ typename Real<PREC>::T adv(typename Real<PREC>::T u1,
-                                                      typename Real<PREC>::T u2,
-                                                      typename Real<PREC>::T xi, double tau,
-                                                      unsigned& amb) {
+__device__ __forceinline__ typename Coord<PREC>::T adv(typename Real<PREC>::T u1,
+                                                       typename Real<PREC>::T u2,
+                                                       typename Coord<PREC>::T xi, double tau,
+                                                       unsigned& amb) {
     if constexpr (PREC == P64) return adv64<CR>(u1, u2, xi, tau, amb);
     else return adv_mix(u1, u2, xi, tau, amb);
 }
@@ -348,7 +363,7 @@ struct Lane {
     unsigned long long hash;
     double t;
     double s_next;      // time of snapshot ks (+inf past the last)
-    R x[3];             // local coordinates
+    typename Coord<PREC>::T x[3];   // local coordinates
     R v1[3], v2[3];     // packed layout: the current cell's face velocities (low, high face)
     int32_t fl;         // packed layout: the current cell's flag word
     int32_t nc0;        // pathline: crossings before this call
@@ -494,7 +509,7 @@ __device__ __forceinline__ void cell_xyz(const GridDev& G, int32_t c, int32_t i,
 template <int PREC, int LAYOUT, int CR>
 __device__ __forceinline__ void eval_snap(const GridDev& G, const typename Real<PREC>::T (&u1)[3],
                                           const typename Real<PREC>::T (&u2)[3],
-                                          const typename Real<PREC>::T (&x)[3], double t, int32_t c,
+                                          const typename Coord<PREC>::T (&x)[3], double t, int32_t c,
                                           int32_t i, int32_t j, int32_t k, double s, double* out,
                                           unsigned& amb) {
     const double tau = s - t;
@@ -509,7 +524,7 @@ template <int PREC, int LAYOUT, int CR>
 __device__ __forceinline__ void snap_at(const GridDev& G, const TrackParams& P,
                                         const typename Real<PREC>::T (&u1)[3],
                                         const typename Real<PREC>::T (&u2)[3],
-                                        const typename Real<PREC>::T (&x)[3], double t, int32_t c, int32_t i,
+                                        const typename Coord<PREC>::T (&x)[3], double t, int32_t c, int32_t i,
                                         int32_t j, int32_t k, int64_t pid, int32_t ks, double s, unsigned& amb) {
     eval_snap<PREC, LAYOUT, CR>(G, u1, u2, x, t, c, i, j, k, s, P.snap_xyz + (pid * P.n_snap + ks) * 3, amb);
 }
@@ -606,7 +621,8 @@ __device__ __forceinline__ void flush_snaps(SnapJob<typename Real<PREC>::T>* W, 
         }
         const SnapJob<R>& J = W[lo];
         const GridDev& G = grid_of<BATCHED>(P, J.g);
-        R u1[3], u2[3], x[3];
+        R u1[3], u2[3];
+        typename Coord<PREC>::T x[3];
         int32_t fl;
         load_rec<PREC>(G, J.c, P.sign, u1, u2, fl);
         x[0] = J.x[0];
@@ -759,9 +775,9 @@ __device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap
     L.c = c;
     L.zrun = 0;
     if constexpr (kTrackIJK<LAYOUT, OUT>) cell_ijk(G, c, L.i, L.j, L.k);
-    L.x[0] = (R)a;
-    L.x[1] = (R)b;
-    L.x[2] = (R)d;
+    L.x[0] = (typename Coord<PREC>::T)a;
+    L.x[1] = (typename Coord<PREC>::T)b;
+    L.x[2] = (typename Coord<PREC>::T)d;
     L.t = t;
     L.ncross = P.ncross[p];
     L.hash = P.hash[p];
@@ -845,8 +861,10 @@ __device__ int32_t quad_transfer(Lane<PREC>& L, const GridDev& G, const TrackPar
     const int ta2 = (axis == 2) ? 1 : 2;
     const double t1 = (ta1 == 0) ? (double)L.x[0] : (double)L.x[1];
     const double t2 = (ta2 == 1) ? (double)L.x[1] : (double)L.x[2];
+    // the last subface is taken when no earlier one holds the point, so it is never tested (a
+    // face with one subface reads no extent)
     int32_t hit = q1 - 1;
-    for (int32_t q = q0; q < q1; ++q) {
+    for (int32_t q = q0; q < q1 - 1; ++q) {
         const double4 r = G.sub_rect[q];
         if (r.x <= t1 && t1 <= r.z && r.y <= t2 && t2 <= r.w) {
             hit = q;
@@ -855,7 +873,10 @@ __device__ int32_t quad_transfer(Lane<PREC>& L, const GridDev& G, const TrackPar
     }
     const int32_t nb = (q1 > q0) ? G.sub_nb[hit] : -1;
     if (nb < 0) return ST_BOUNDARY;
-    const int32_t nfl = G.rec64[nb].flags;
+    // the neighbour's record, gathered at once (its flags decide the transfer; the velocities
+    // of the cell left are not read again)
+    load_rec<PREC>(G, nb, P.sign, L.v1, L.v2, L.fl);
+    const int32_t nfl = L.fl;
     if (!(nfl & CF_ACTIVE)) return ST_INACTIVE_NB;
     const QuadBox& B = G.qbox[L.c];
     const QuadBox& N = G.qbox[nb];
@@ -892,7 +913,24 @@ __device__ int32_t quad_transfer(Lane<PREC>& L, const GridDev& G, const TrackPar
     } else {
         L.zrun = 0;
     }
-    load_rec<PREC>(G, L.c, P.sign, L.v1, L.v2, L.fl);
+    return 0;
+}
+
+// End of a time step (transient flow): the particle continues in the next step's field from the
+// same cell and position; it stops there if the cell is inactive, or a sink with stop_at_sink.
+template <int PREC, int LAYOUT, bool BATCHED>
+__device__ __forceinline__ int32_t step_switch(Lane<PREC>& L, const TrackParams& P) {
+    L.g += 1;
+    const GridDev& G2 = grid_of<BATCHED>(P, L.g);
+    int32_t own;
+    if constexpr (kPacked<LAYOUT>) {
+        load_rec<PREC>(G2, L.c, P.sign, L.v1, L.v2, L.fl);
+        own = L.fl;
+    } else {
+        own = G2.flags[L.c];
+    }
+    if (!(own & CF_ACTIVE)) return ST_INACTIVE_NB;
+    if ((own & CF_SINK) && P.stop_at_sink) return ST_SINK;
     return 0;
 }
 
@@ -955,72 +993,66 @@ __device__ __forceinline__ int32_t track_step(Lane<PREC>& L, const TrackParams& 
         return ST_STRANDED;
     }
     const double t_exit = L.t + dt;
-    if (t_exit > lim) {
-        const double tau = lim - L.t;
-        if constexpr (OUT == O_SERIES) write_snaps<PREC, LAYOUT, CR>(L, G, u1, u2, P, snap, lim, true);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if constexpr (PREC == P64) L.x[a] = adv64_au<CR>(Aa[a], upa[a], L.x[a], tau, L.amb);
-            else L.x[a] = adv<PREC, CR>(u1[a], u2[a], L.x[a], tau, L.amb);
-        }
-        L.t = lim;
-        if constexpr (BATCHED) {
-            if (next_step) {
-                // end of the time step: the next step's field, same cell and position
-                L.g += 1;
-                const GridDev& G2 = grid_of<BATCHED>(P, L.g);
-                int32_t own;
-                if constexpr (kPacked<LAYOUT>) {
-                    load_rec<PREC>(G2, L.c, P.sign, L.v1, L.v2, L.fl);
-                    own = L.fl;
-                } else {
-                    own = G2.flags[L.c];
-                }
-                if (!(own & CF_ACTIVE)) return ST_INACTIVE_NB;
-                if ((own & CF_SINK) && P.stop_at_sink) return ST_SINK;
-                return 0;
-            }
-        }
-        return axis < 0 ? ST_STRANDED : ST_MAX_TIME;
-    }
+    // The limit comes first: every axis moves analytically to it and no face is crossed.  The
+    // two axes other than the exit axis (axis 0 when no face is reachable) move by the same
+    // code as in a crossing step, so lanes of a wave that stop at a limit (or at the end of a
+    // time step) and lanes that cross a face diverge only in the exit axis' own advance.
+    const bool at_lim = t_exit > lim;
+    const double tau = at_lim ? lim - L.t : dt;
 
     const int32_t hi = (xe == (R)1) ? 1 : 0;
     const int32_t f = 2 * axis + hi;
     const int32_t step = hi ? 1 : -1;
 
-    // advance to the exit face: the two other axes move analytically
     if constexpr (OUT == O_SERIES) {
-        if (job) queue_snaps<PREC, LAYOUT, CR>(L, G, u1, u2, P, snap, t_exit, job);
+        if (at_lim) write_snaps<PREC, LAYOUT, CR>(L, G, u1, u2, P, snap, lim, true);
+        else if (job) queue_snaps<PREC, LAYOUT, CR>(L, G, u1, u2, P, snap, t_exit, job);
         else write_snaps<PREC, LAYOUT, CR>(L, G, u1, u2, P, snap, t_exit, false);
     }
     {
-        const int a1 = (axis == 0) ? 1 : 0;
-        const int a2 = (axis == 2) ? 1 : 2;
-        const R v1a = (a1 == 0) ? u1[0] : u1[1];
-        const R v2a = (a1 == 0) ? u2[0] : u2[1];
-        const R xa = (a1 == 0) ? L.x[0] : L.x[1];
-        const R v1b = (a2 == 1) ? u1[1] : u1[2];
-        const R v2b = (a2 == 1) ? u2[1] : u2[2];
-        const R xb = (a2 == 1) ? L.x[1] : L.x[2];
-        R na, nb;
+        const int ae = axis < 0 ? 0 : axis;
+        const int a1 = (ae == 0) ? 1 : 0;
+        const int a2 = (ae == 2) ? 1 : 2;
+        const typename Coord<PREC>::T xa = (a1 == 0) ? L.x[0] : L.x[1];
+        const typename Coord<PREC>::T xb = (a2 == 1) ? L.x[1] : L.x[2];
+        typename Coord<PREC>::T na, nb, ne = xe;
         if constexpr (PREC == P64) {
             const double Ax = (a1 == 0) ? Aa[0] : Aa[1], ux = (a1 == 0) ? upa[0] : upa[1];
             const double Ay = (a2 == 1) ? Aa[1] : Aa[2], uy = (a2 == 1) ? upa[1] : upa[2];
-            (void)v1a, (void)v2a, (void)v1b, (void)v2b;
-            na = adv64_au<CR>(Ax, ux, xa, dt, L.amb);
-            nb = adv64_au<CR>(Ay, uy, xb, dt, L.amb);
+            na = adv64_au<CR>(Ax, ux, xa, tau, L.amb);
+            nb = adv64_au<CR>(Ay, uy, xb, tau, L.amb);
+            if (at_lim) {
+                const double Ae = (ae == 0) ? Aa[0] : ((ae == 1) ? Aa[1] : Aa[2]);
+                const double ue = (ae == 0) ? upa[0] : ((ae == 1) ? upa[1] : upa[2]);
+                const double xc = (ae == 0) ? L.x[0] : ((ae == 1) ? L.x[1] : L.x[2]);
+                ne = adv64_au<CR>(Ae, ue, xc, tau, L.amb);
+            }
         } else {
             // the gradient and particle velocity as the exit times formed them
             const float A0 = u2[0] - u1[0], A1 = u2[1] - u1[1], A2 = u2[2] - u1[2];
-            const float p0 = fmaf(A0, L.x[0], u1[0]), p1 = fmaf(A1, L.x[1], u1[1]), p2 = fmaf(A2, L.x[2], u1[2]);
-            (void)v1a, (void)v2a, (void)v1b, (void)v2b;
-            na = adv_mix_au((a1 == 0) ? A0 : A1, (a1 == 0) ? p0 : p1, xa, dt);
-            nb = adv_mix_au((a2 == 1) ? A1 : A2, (a2 == 1) ? p1 : p2, xb, dt);
+            const float p0 = fmaf(A0, (float)L.x[0], u1[0]), p1 = fmaf(A1, (float)L.x[1], u1[1]),
+                        p2 = fmaf(A2, (float)L.x[2], u1[2]);
+            na = adv_mix_au((a1 == 0) ? A0 : A1, (a1 == 0) ? p0 : p1, xa, tau);
+            nb = adv_mix_au((a2 == 1) ? A1 : A2, (a2 == 1) ? p1 : p2, xb, tau);
+            if (at_lim) {
+                // the same gradient and velocity, formed again from the face velocities
+                const typename Coord<PREC>::T xc = (ae == 0) ? L.x[0] : ((ae == 1) ? L.x[1] : L.x[2]);
+                ne = adv_mix((ae == 0) ? u1[0] : ((ae == 1) ? u1[1] : u1[2]),
+                             (ae == 0) ? u2[0] : ((ae == 1) ? u2[1] : u2[2]), xc, tau, L.amb);
+            }
         }
-        L.x[0] = (axis == 0) ? xe : na;
-        L.x[1] = (axis == 1) ? xe : ((a1 == 1) ? na : nb);
-        L.x[2] = (axis == 2) ? xe : nb;
+        L.x[0] = (ae == 0) ? ne : na;
+        L.x[1] = (ae == 1) ? ne : ((a1 == 1) ? na : nb);
+        L.x[2] = (ae == 2) ? ne : nb;
     }
+    if (at_lim) {
+        L.t = lim;
+        if constexpr (BATCHED) {
+            if (next_step) return step_switch<PREC, LAYOUT, BATCHED>(L, P);
+        }
+        return axis < 0 ? ST_STRANDED : ST_MAX_TIME;
+    }
+
     L.t = t_exit;
     L.ncross += 1;
     crossings += 1;
@@ -1238,6 +1270,13 @@ k_track_static(TrackParams P) {
     block_flush(S, P, crossings, L.amb, L.drop);
 }
 
+// Lane 0's value of a 64-bit quantity as a wave-uniform (scalar) value.
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 template <int PREC, int LAYOUT, int OUT, bool BATCHED>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesPersistent<PREC, OUT>)))
 k_track_persistent(TrackParams P) {
@@ -1273,7 +1312,7 @@ k_track_persistent(TrackParams P) {
                 const unsigned long long hi = (lo + seg < n) ? lo + seg : n;
                 unsigned long long base = 0;
                 if ((threadIdx.x & 63) == 0) base = atomicAdd(&P.counters->queue[sg], chunk);
-                base = lo + __shfl(base, 0, 64);
+                base = lo + uniform_u64(base);   // lane 0's claim, kept in scalar registers
                 if (base < hi) {
                     nbase = base;
                     nlen = (hi - base < chunk) ? hi - base : chunk;
