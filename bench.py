@@ -162,9 +162,12 @@ class Case:
         wall = time.perf_counter() - t0
         cross = summ[0]["crossings"]
         assert all(s["crossings"] == cross for s in summ), "crossing count changed between steps"
-        kms = float(np.mean([s["kernel_ms"] for s in summ]))
+        # the tracking kernel's own device time (events just around its launch), and that of the
+        # whole pt_track sequence (counter reset, ordering sort, tracking kernel, careful pass)
+        kms = float(np.mean([s["track_ms"] for s in summ]))
+        cms = float(np.mean([s["kernel_ms"] for s in summ]))
         return dict(wall_s=wall, ms_per_step=1e3 * wall / steps, crossings_per_step=cross,
-                    value=cross * steps / wall, kernel_ms=kms, summary=summ[0])
+                    value=cross * steps / wall, kernel_ms=kms, call_ms=cms, summary=summ[0])
 
     def time_pathline(self, precision, schedule_name, steps, warmup, **kw):
         """One step = restore the state, the count pass (offsets), the record pass (one record
@@ -270,6 +273,7 @@ def roofline(res, n, precision, workload, schedule, timeseries=False, batched=Fa
            "frac": round(achieved / HBM_PEAK_GBS, 5),
            "traffic": profiled_traffic(workload, precision, schedule),
            "bytes_per_launch": int(bytes_launch), "kernel_ms": round(res["kernel_ms"], 4),
+           "call_ms": round(res["call_ms"], 4),
            "kernel": kernel_name(precision, schedule, timeseries, batched)}
     # the vector-ALU view of the same kernel, from the committed instruction counters: issued VALU
     # cycles over the available ones, and the FP64 arithmetic rate (add, multiply, transcendental:

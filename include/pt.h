@@ -293,6 +293,9 @@ typedef struct {
                                    * careful pass that decides such arguments exactly.  Beyond   *
                                    * 2^20 per call (2^18 for pt_track_noalloc) the rest keep     *
                                    * their first results and count in cr_ambiguous.              */
+    double track_ms;              /* device time of the tracking kernel alone (events recorded   *
+                                   * just before and after its launch; kernel_ms also encloses   *
+                                   * the counter reset, the ordering sort and the careful pass)  */
 } pt_summary;
 
 /* Wait for the run, then fill *out.  Reports asynchronous device errors of

@@ -126,6 +126,7 @@ struct pt_run {
     Counters* d_counters = nullptr;
     Counters* h_counters = nullptr;     // pinned
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_done = nullptr;
+    hipEvent_t evk0 = nullptr, evk1 = nullptr;   // around the tracking kernel alone
     bool launched = false;
     int sched = 0, layout = 0, block = 0, grid = 0;
     // per-run device tables (batched runs, snapshot times) and their pinned staging
@@ -159,6 +160,8 @@ void destroy_run(pt_run* r) {
     if (r->ev0) (void)hipEventDestroy(r->ev0);
     if (r->ev1) (void)hipEventDestroy(r->ev1);
     if (r->ev_done) (void)hipEventDestroy(r->ev_done);
+    if (r->evk0) (void)hipEventDestroy(r->evk0);
+    if (r->evk1) (void)hipEventDestroy(r->evk1);
     if (r->d_counters) (void)hipFree(r->d_counters);
     if (r->h_counters) (void)hipHostFree(r->h_counters);
     if (r->d_tables) (void)hipFree(r->d_tables);
@@ -189,6 +192,8 @@ int new_run(int device, pt_run** out) {
     if (e == hipSuccess) e = hipEventCreate(&r->ev0);
     if (e == hipSuccess) e = hipEventCreate(&r->ev1);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&r->evk0);
+    if (e == hipSuccess) e = hipEventCreate(&r->evk1);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         destroy_run(r);
@@ -661,6 +666,7 @@ void bind_params(const Plan& PL, const pt_grid* const* grids, int32_t n_grids, c
 struct LaunchSeq {
     Launch v[16];
     int n = 0;
+    int track_at = -1;   // index of the tracking kernel
     void push(const void* fn, dim3 grid, dim3 block, void* arg, size_t bytes, size_t lds = 0) {
         v[n].fn = fn;
         v[n].grid = grid;
@@ -689,6 +695,7 @@ void build_seq(const Plan& PL, int64_t n, Counters** cptr, TrackParams* P, SortP
                 seq.push(sort_scan_add_kernel(), dim3((unsigned)SP->ntiles), dim3(kScanBlock), SP, sizeof *SP);
             seq.push(sort_scatter_kernel(), dim3(nb), dim3(256), SP, sizeof *SP);
         }
+        seq.track_at = seq.n;
         seq.push(PL.fn, dim3(PL.grid), dim3(PL.block), P, sizeof *P, PL.lds);
         if (PL.recheck_cap > 0) {
             // careful pass: a fixed grid that strides over the (usually empty) lists
@@ -778,7 +785,7 @@ struct TableFill {
 // =============================================================================================
 extern "C" {
 
-int pt_version(void) { return 103; }
+int pt_version(void) { return 104; }
 
 const char* pt_last_error(void) { return g_err.c_str(); }
 
@@ -1125,6 +1132,12 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
                 e = hipGraphCreate(&gr, 0);
                 hipGraphNode_t prev = nullptr;
                 for (int q = 0; e == hipSuccess && q < seq.n; ++q) {
+                    if (q == seq.track_at) {   // event nodes around the tracking kernel
+                        hipGraphNode_t ev = nullptr;
+                        e = hipGraphAddEventRecordNode(&ev, gr, prev ? &prev : nullptr, prev ? 1 : 0, r->evk0);
+                        prev = ev;
+                        if (e != hipSuccess) break;
+                    }
                     void* args[] = {seq.v[q].arg};
                     hipKernelNodeParams kp;
                     std::memset(&kp, 0, sizeof kp);
@@ -1136,6 +1149,11 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
                     hipGraphNode_t node = nullptr;
                     e = hipGraphAddKernelNode(&node, gr, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
                     prev = node;
+                    if (e == hipSuccess && q == seq.track_at) {
+                        hipGraphNode_t ev = nullptr;
+                        e = hipGraphAddEventRecordNode(&ev, gr, &prev, 1, r->evk1);
+                        prev = ev;
+                    }
                 }
                 if (e == hipSuccess) e = hipGraphInstantiate(&r->exec, gr, nullptr, nullptr, 0);
                 if (e == hipSuccess) {
@@ -1148,8 +1166,11 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
             }
             if (e == hipSuccess) e = hipGraphLaunch(r->exec, s);
         } else {
-            for (int q = 0; e == hipSuccess && q < seq.n; ++q)
-                e = launch(seq.v[q].fn, seq.v[q].grid, seq.v[q].block, seq.v[q].arg, seq.v[q].lds, s);
+            for (int q = 0; e == hipSuccess && q < seq.n; ++q) {
+                if (q == seq.track_at) e = hipEventRecord(r->evk0, s);
+                if (e == hipSuccess) e = launch(seq.v[q].fn, seq.v[q].grid, seq.v[q].block, seq.v[q].arg, seq.v[q].lds, s);
+                if (e == hipSuccess && q == seq.track_at) e = hipEventRecord(r->evk1, s);
+            }
         }
     }
     if (e == hipSuccess) e = hipEventRecord(r->ev1, s);
@@ -1223,6 +1244,8 @@ int pt_results(pt_run* r, pt_summary* out) {
     HIP_TRY(hipEventSynchronize(r->ev_done));
     float ms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, r->ev0, r->ev1));
+    float kms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&kms, r->evk0, r->evk1));
     std::memset(out, 0, sizeof *out);
     const Counters& c = *r->h_counters;
     out->crossings = (int64_t)c.crossings;
@@ -1233,6 +1256,7 @@ int pt_results(pt_run* r, pt_summary* out) {
     }
     out->n_tracked = tracked;
     out->kernel_ms = ms;
+    out->track_ms = kms;
     out->schedule = r->sched;
     out->layout = r->layout;
     out->block = r->block;

@@ -86,7 +86,7 @@ class pt_summary(ctypes.Structure):
                 ("schedule", ctypes.c_int32), ("layout", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("cr_ambiguous", ctypes.c_int64),
                 ("path_records", ctypes.c_int64), ("path_dropped", ctypes.c_int64),
-                ("recheck_tracks", ctypes.c_int64)]
+                ("recheck_tracks", ctypes.c_int64), ("track_ms", ctypes.c_double)]
 
 
 EXPORTS = ["pt_load_grid", "pt_load_quad_grid", "pt_track", "pt_track_noalloc", "pt_results", "pt_release",
@@ -400,7 +400,7 @@ def pt_results(run: Run) -> dict:
     return dict(crossings=s.crossings, n_tracked=s.n_tracked, status_count=list(s.status_count),
                 kernel_ms=s.kernel_ms, schedule=s.schedule, layout=s.layout, block=s.block, grid=s.grid,
                 cr_ambiguous=s.cr_ambiguous, path_records=s.path_records, path_dropped=s.path_dropped,
-                recheck_tracks=s.recheck_tracks)
+                recheck_tracks=s.recheck_tracks, track_ms=s.track_ms)
 
 
 # --------------------------------------------------------------------------------------------- helper

@@ -41,6 +41,6 @@ int main(void) {
     F(pt_summary, crossings); F(pt_summary, n_tracked); F(pt_summary, status_count);
     F(pt_summary, kernel_ms); F(pt_summary, schedule); F(pt_summary, layout); F(pt_summary, block);
     F(pt_summary, grid); F(pt_summary, cr_ambiguous); F(pt_summary, path_records);
-    F(pt_summary, path_dropped); F(pt_summary, recheck_tracks);
+    F(pt_summary, path_dropped); F(pt_summary, recheck_tracks); F(pt_summary, track_ms);
     return 0;
 }

@@ -70,7 +70,7 @@ def test_path_record_host_dtype_matches_struct():
 
 
 def test_version_and_defaults(lib):
-    assert lib.pt_version() == 103
+    assert lib.pt_version() == 104
     o = pt.pt_default_opts()
     assert (o.mode, o.precision, o.schedule, o.layout) == (0, 0, 0, 0)
     assert o.direction == 1 and o.stop_at_sink == 1 and math.isinf(o.t_max) and o.max_steps == 1 << 20
