@@ -1310,14 +1310,18 @@ k_track_persistent(TrackParams P) {
                 const int sg = (die + tried) % kXcd;
                 const unsigned long long lo = (unsigned long long)sg * seg;
                 const unsigned long long hi = (lo + seg < n) ? lo + seg : n;
+                // one claim covers every idle lane: at least a chunk, more when more lanes are idle
+                // (a wave's first fill takes 64 consecutive slots, as in the static kernel)
+                const unsigned long long want = (unsigned long long)nidle - avail;
+                const unsigned long long amount = want > chunk ? want : chunk;
                 unsigned long long base = 0;
-                if ((threadIdx.x & 63) == 0) base = atomicAdd(&P.counters->queue[sg], chunk);
+                if ((threadIdx.x & 63) == 0) base = atomicAdd(&P.counters->queue[sg], amount);
                 base = lo + uniform_u64(base);   // lane 0's claim, kept in scalar registers
                 if (base < hi) {
                     nbase = base;
-                    nlen = (hi - base < chunk) ? hi - base : chunk;
+                    nlen = (hi - base < amount) ? hi - base : amount;
                 }
-                if (base + chunk >= hi) {
+                if (base + amount >= hi) {
                     ++tried;
                     if (tried == kXcd) exhausted = true;
                 }
