@@ -474,6 +474,7 @@ def main():
             tag = "%s_%s_%s" % (wname, prec, s2)
             v = dict(value=r["value"], ms_per_step=round(r["ms_per_step"], 4),
                      kernel_ms=round(r["kernel_ms"], 4), crossings_per_step=r["crossings_per_step"],
+                     recheck_tracks=r["summary"]["recheck_tracks"],
                      launch=p2, roofline_frac=roofline(r, n, prec, wname, s2, mode == "timeseries", batched)["frac"])
             if prec == "mixed" and ref_state is not None:
                 mix = state_of(case)
@@ -551,6 +552,10 @@ def main():
                    "grid": primary["summary"]["grid"]},
         "roofline": roofline(primary, n, args.precision, args.workload, primary["schedule"],
                              primary["mode"] == "timeseries", primary["batched"]),
+        # FP64: particles handed to the careful pass (an evaluation within 2^-96 of a rounding
+        # boundary) and evaluations left undecided, in the last timed step
+        "rounding": {"recheck_tracks": primary["summary"]["recheck_tracks"],
+                     "cr_ambiguous": primary["summary"]["cr_ambiguous"]},
     }
     if want_cpu:
         idx, r = oracle_for_accuracy(w)
@@ -585,6 +590,7 @@ def main():
                                           small_oracle_sample if (wname == "C5" and want_cpu) else None)
             variants["%s_fp64_%s" % (wname, pr["schedule"])] = dict(
                 value=pr["value"], ms_per_step=round(pr["ms_per_step"], 4), kernel_ms=round(pr["kernel_ms"], 4),
+                recheck_tracks=pr["summary"]["recheck_tracks"],
                 crossings_per_step=pr["crossings_per_step"], launch=pr["params"],
                 roofline_frac=roofline(pr, pr["n"], "fp64", wname, pr["schedule"], pr["mode"] == "timeseries",
                                        pr["batched"])["frac"], workload=DESCR[wname])
