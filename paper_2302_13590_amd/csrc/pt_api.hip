@@ -1155,6 +1155,12 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
                         prev = ev;
                     }
                 }
+                // no tracking kernel (no particles): both events at the end, track_ms = 0
+                for (int q = 0; e == hipSuccess && seq.track_at < 0 && q < 2; ++q) {
+                    hipGraphNode_t ev = nullptr;
+                    e = hipGraphAddEventRecordNode(&ev, gr, prev ? &prev : nullptr, prev ? 1 : 0, q ? r->evk1 : r->evk0);
+                    prev = ev;
+                }
                 if (e == hipSuccess) e = hipGraphInstantiate(&r->exec, gr, nullptr, nullptr, 0);
                 if (e == hipSuccess) {
                     r->graph = gr;
@@ -1171,6 +1177,8 @@ int pt_track(const pt_grid* const* grids, int32_t n_grids, const pt_particles* p
                 if (e == hipSuccess) e = launch(seq.v[q].fn, seq.v[q].grid, seq.v[q].block, seq.v[q].arg, seq.v[q].lds, s);
                 if (e == hipSuccess && q == seq.track_at) e = hipEventRecord(r->evk1, s);
             }
+            if (e == hipSuccess && seq.track_at < 0) e = hipEventRecord(r->evk0, s);
+            if (e == hipSuccess && seq.track_at < 0) e = hipEventRecord(r->evk1, s);
         }
     }
     if (e == hipSuccess) e = hipEventRecord(r->ev1, s);

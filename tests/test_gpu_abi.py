@@ -151,3 +151,23 @@ def test_shutdown_releases_everything_and_library_restarts(pt):
     r = O.track(g, p)
     out = gpu_track([g], p, use_graph=1)
     compare(out, r, label="after shutdown", spacing=(10.0, 10.0, 10.0))
+
+
+def test_kernel_time_events(pt):
+    """track_ms times the tracking kernel alone: positive, inside the whole call's kernel_ms, in
+    graph and eager launches; a call without particles (no tracking kernel) reports ~0 (its two
+    events are recorded back to back), also on a pooled run whose events an earlier call recorded."""
+    import torch
+    g = C.random_grid(30, 20, 5, 1.0, 4.0, 72)
+    h = pt.pt_load_grid(g)
+    w = C.release(np.random.Generator(np.random.PCG64(9)), 50000, g.nx, g.ny, g.nz)
+    empty = C.release(np.random.Generator(np.random.PCG64(9)), 0, g.nx, g.ny, g.nz)
+    for graph in (0, 1):
+        for rep in range(3):
+            s = pt.track([h], pt.DeviceParticles.from_numpy(w), use_graph=graph, sort=pt.PT_SORT_CELL)
+            assert s["crossings"] > 0
+            assert 0.0 < s["track_ms"] <= s["kernel_ms"], (graph, rep, s["track_ms"], s["kernel_ms"])
+            e = pt.track([h], pt.DeviceParticles.from_numpy(empty), use_graph=graph)
+            assert e["crossings"] == 0 and 0.0 <= e["track_ms"] < 0.05, (graph, rep, e)
+    torch.cuda.synchronize()
+    h.release()
