@@ -553,7 +553,7 @@ def main():
         "roofline": roofline(primary, n, args.precision, args.workload, primary["schedule"],
                              primary["mode"] == "timeseries", primary["batched"]),
         # FP64: particles handed to the careful pass (an evaluation within 2^-96 of a rounding
-        # boundary) and evaluations left undecided, in the last timed step
+        # boundary) and evaluations left undecided, in the first timed step
         "rounding": {"recheck_tracks": primary["summary"]["recheck_tracks"],
                      "cr_ambiguous": primary["summary"]["cr_ambiguous"]},
     }
