@@ -338,6 +338,30 @@ def fp64_parity(state, r, idx):
             "reference": "the FP64 oracle (plain CPU tracker) on the CPU-baseline sample"}
 
 
+def oracle_full(wname, threads, chunk=100_000):
+    """The CPU oracle over every particle of workload wname (crossings/s on `threads` threads), in
+    chunks of `chunk` consecutive particles timed one after another, with a progress line per chunk.
+    The full-workload counterpart of the benchmark's bounded cpu_baseline sample; one JSON line."""
+    if wname not in ("C1", "C2", "C3", "C4", "C5"):
+        print("--oracle-full times the structured steady workloads C1-C5", file=sys.stderr)
+        return 2
+    w = workload(wname)
+    n = w.particles.n
+    total_s, total_cross = 0.0, 0
+    for lo in range(0, n, chunk):
+        idx = np.arange(lo, min(n, lo + chunk))
+        r, dt = oracle_on_sample(w, idx, threads)
+        total_s += dt
+        total_cross += int(r.ncross.astype(np.int64).sum())
+        log("oracle %s: particles %d..%d, %.1f s so far, %.4g crossings/s" % (
+            wname, lo, idx[-1], total_s, total_cross / total_s))
+    print(json.dumps({"kind": "oracle", "workload": DESCR[wname], "threads": threads, "particles": n,
+                      "crossings": total_cross, "seconds": round(total_s, 2),
+                      "value": total_cross / total_s, "unit": "cell-crossings/s", "cpu_model": host_cpu_model(),
+                      "host_cores_visible": len(os.sched_getaffinity(0))}), flush=True)
+    return 0
+
+
 # launch parameters of the scheduling study (the tuned C2/C3 shapes of each kernel)
 STUDY_LAUNCH = {"static": dict(block=256), "persistent": dict(block=256, refill=1, chunk=32, steps_per_refill=2)}
 
@@ -402,10 +426,16 @@ def main():
     ap.add_argument("--study", choices=["scheduling"],
                     help="instead of the benchmark line: static vs persistent on the first test case's "
                          "shape over variances and particle counts")
+    ap.add_argument("--oracle-full", action="store_true",
+                    help="instead of the benchmark line: the CPU oracle alone over every particle of the "
+                         "workload on --oracle-threads threads, in chunks of 1e5 particles (no GPU)")
+    ap.add_argument("--oracle-threads", type=int, default=1)
     ap.add_argument("--study-sigma2", default="0.1,1,2.5,5")
     ap.add_argument("--study-np", default="1e3,1e4,1e5,1e6,1e7")
     args = ap.parse_args()
 
+    if args.oracle_full:
+        return oracle_full(args.workload, args.oracle_threads)
     if args.gpus != 1:
         print("bench.py measures one GPU: the tracker runs on a single MI355X (particles are independent, "
               "so the path would shard by particle with no exchange until a final reduction of the counters).",
