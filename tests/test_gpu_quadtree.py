@@ -130,7 +130,7 @@ def test_c7_full_sampled(pt):
     out = gpu_track([q], p, **bench_opts("C7"))
     s = out["summary"]
     assert s["crossings"] == int(out["ncross"].astype(np.int64).sum())
-    idx = sample_indices(p.n, 3000, seed=81)
+    idx = sample_indices(p.n, 100_000, seed=81)
     r = O.track_quad(q, p.subset(idx))
     compare(out, r, idx=idx, label="C7", spacing=(2.5, 2.5, 5.0))
     print("C7 crossings %d statuses %s kernel ms %.3f" % (s["crossings"], s["status_count"], s["kernel_ms"]))

@@ -168,7 +168,7 @@ def test_c6_full_sampled(pt):
     out = gpu_track(w.grids, p, tstep_end=w.tstep_end, stop_at_sink=w.stop_at_sink, **bench_opts("C6"))
     s = out["summary"]
     assert s["crossings"] == int(out["ncross"].astype(np.int64).sum())
-    idx = sample_indices(p.n, 3000, seed=61)
+    idx = sample_indices(p.n, 100_000, seed=61)
     r = O.track_transient(w.grids, w.tstep_end, p.subset(idx), stop_at_sink=w.stop_at_sink)
     compare(out, r, idx=idx, label="C6", spacing=(10.0, 10.0, 2.0))
     print("C6 crossings %d statuses %s kernel ms %.3f" % (s["crossings"], s["status_count"], s["kernel_ms"]))
