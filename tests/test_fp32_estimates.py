@@ -55,8 +55,15 @@ def estimate(D, up, A, ue, rng, with_unsure=False):
     if not with_unsure:
         return E
     lo, hi = F(2.0 ** -100), F(2.0 ** 100)
-    unsure = ~(q >= lo) | ~(np.abs(Df) >= lo) | (ratio & ~(np.abs(uef) >= lo))
-    unsure |= ~((np.abs(upf) >= lo) & (np.abs(upf) <= hi)) | ~((E >= lo) & (E <= F(2.0 ** 120)))
+    # the kernel's form: one minimum over the operands (fminf, like np.fmin, ignores a NaN), then
+    # NaN-safe range tests of |u_p| and of the estimate
+    m = np.fmin(np.fmin(np.abs(Df), np.abs(upf)), np.fmin(q, np.where(ratio, np.abs(uef), F(1.0))))
+    unsure = ~(m >= lo) | ~(np.abs(upf) <= hi) | ~((E >= lo) & (E <= F(2.0 ** 120)))
+    # the same set as testing every operand on its own: a NaN q comes only with a zero distance or
+    # a |u_p| outside [2^-100, 2^100], which the minimum or the |u_p| test catch
+    each = ~(q >= lo) | ~(np.abs(Df) >= lo) | (ratio & ~(np.abs(uef) >= lo))
+    each |= ~((np.abs(upf) >= lo) & (np.abs(upf) <= hi)) | ~((E >= lo) & (E <= F(2.0 ** 120)))
+    assert np.array_equal(unsure, each)
     return E, unsure
 
 
@@ -207,3 +214,25 @@ def test_estimate_bounded_whenever_trusted():
             worst = max(worst, float(rel.max()))
     assert trusted > total // 4 and trusted < total     # both outcomes occur in this range
     assert worst < BOUND, worst
+
+
+def test_unsure_on_degenerate_operands():
+    """Operands that make the FP32 estimate NaN or meaningless (a zero distance, a particle
+    velocity that rounds to zero, FP32 subnormal or beyond the FP32 range, gradients and face
+    velocities beyond the FP32 range) always raise the flag; the kernel's single-minimum form of
+    the range test flags exactly what testing every operand on its own flags (estimate() checks
+    that equality on every call)."""
+    rng = np.random.default_rng(5)
+    cases = [  # D, u_p, A, u_e
+        (0.0, 1.0, 1e39, 2.0),          # zero distance, gradient beyond FP32: A * 0 = inf * 0
+        (0.0, 1e-50, 0.0, 1e-50),       # zero distance, u_p rounds to zero: 0 * inf
+        (0.5, 1e-50, 1.0, 1.0),         # u_p below the FP32 range
+        (0.5, 1e-41, 1.0, 1.0),         # u_p FP32-subnormal
+        (0.5, 1e39, -1e39, 1e39),       # u_p beyond the FP32 range
+        (0.5, 1e20, -4e39, -1e39),      # gradient beyond FP32, strong deceleration
+        (1e-44, 1.0, 1.0, 2.0),         # distance FP32-subnormal
+        (0.5, -1.0, 1e38, -1e-45),      # ratio form with u_e below the FP32 range
+    ]
+    D, up, A, ue = (np.array(c, dtype=np.float64) for c in zip(*cases))
+    E, uns = estimate(D, up, A, ue, rng, with_unsure=True)
+    assert uns.all(), (E, uns)
