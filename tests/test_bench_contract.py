@@ -34,6 +34,18 @@ def test_bench_line():
     rf = d["roofline"]
     assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
     assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-4
+    assert 0.0 < rf["kernel_ms"] <= rf["call_ms"] <= d["ms_per_step"] * 1.05
+    assert d["rounding"]["recheck_tracks"] >= 0 and d["rounding"]["cr_ambiguous"] == 0
+
+
+def test_oracle_full_command():
+    """bench.py --oracle-full: the oracle over every particle of a workload, one JSON line."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--oracle-full", "--workload", "C1"],
+                       capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    assert d["kind"] == "oracle" and d["particles"] == 1000 and d["crossings"] == 40000   # 40 cells per row
+    assert d["threads"] == 1 and d["value"] > 0
 
 
 def test_path_accuracy_report():
