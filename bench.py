@@ -421,6 +421,9 @@ def main():
                     help="time only the chosen workload's variants, not the other workloads")
     ap.add_argument("--cpu-sample", type=int, default=500_000,
                     help="particles of the oracle's all-threads sample (the one-thread leg takes a tenth)")
+    ap.add_argument("--lib", default=None,
+                    help="load this build of libpt.so instead of the in-tree one (e.g. a copy of the "
+                         "sources built with python -m paper_2302_13590_amd.build --src DIR --out PATH)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain elementwise copy of this many bytes (HBM-counter calibration)")
     ap.add_argument("--study", choices=["scheduling"],
@@ -447,7 +450,10 @@ def main():
         return 1
     from paper_2302_13590_amd import accuracy as ACC
     from paper_2302_13590_amd import pt
-    pt.load_library()
+    if args.lib:
+        pt.load_library(os.path.abspath(args.lib))
+    else:
+        pt.load_library()
     if args.study == "scheduling":
         return scheduling_study([float(v) for v in args.study_sigma2.split(",")],
                                 [int(float(v)) for v in args.study_np.split(",")], max(1, args.steps // 3))

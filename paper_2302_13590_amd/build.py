@@ -1,6 +1,7 @@
 """Build libpt.so (HIP, gfx950) in-tree with hipcc.
 
     python -m paper_2302_13590_amd.build
+    python -m paper_2302_13590_amd.build --src DIR --out PATH   # a library from another copy of csrc/
 """
 from __future__ import annotations
 
@@ -31,17 +32,21 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-I", INCLUDE, "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+def build(verbose: bool = False, src: str = CSRC, out: str = LIB) -> str:
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + ["-I", INCLUDE, "-o", tmp] + [os.path.join(src, s) for s in SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose=True)
-    print(LIB)
+    import argparse
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--src", default=CSRC, help="directory holding pt_kernels.hip and pt_api.hip")
+    ap.add_argument("--out", default=LIB)
+    a = ap.parse_args()
+    print(build(verbose=True, src=os.path.abspath(a.src), out=os.path.abspath(a.out)))
     sys.exit(0)
