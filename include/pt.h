@@ -317,8 +317,9 @@ int pt_release(void* handle);
  * per GPU, held until the process ends.  Limits (PT_ERR_UNSUPPORTED beyond them): the tables of
  * one call -- a 160-byte view per grid for batched or transient runs, the group table, the
  * snapshot times, the time-step ends -- at most 64 KiB; a pathline count pass at most 2^26
- * particles; ordering by starting cell (PT_SORT_CELL) only while 12 bytes per particle plus
- * 4 bytes per cell fit in the remaining ~30.9 MiB (PT_SORT_AUTO then simply does not order).
+ * particles; ordering by starting cell (PT_SORT_CELL) only while its buffers -- 16 bytes per
+ * particle plus 4 bytes per tile of 4096 particles and super-bucket (at most 256 super-buckets up
+ * to 2.1e6 cells) -- fit in the remaining ~30.9 MiB (PT_SORT_AUTO then simply does not order).
  *
  * The run's counts are written, once its kernels have run, to `counts` (device memory owned by
  * the caller, PT_COUNTS_WORDS int64): PT_COUNT_CROSSINGS, PT_COUNT_TRACKED,
@@ -331,7 +332,7 @@ int pt_release(void* handle);
  * Every call on one GPU uses that GPU's single scratch array, which keeps the last call's
  * contents: calls whose work overlaps on one GPU (other streams or threads, before the previous
  * call's kernels finished) race and give wrong results.  Calls on one stream are ordered and safe.
- * The call clears what must start at zero (counters, ordering histogram) with kernels, not
+ * The call clears what must start at zero (the counters) with kernels, not
  * memsets.  Errors: as pt_track; PT_ERR_INVALID_ARG for counts == NULL.
  */
 #define PT_NOALLOC_SCRATCH_BYTES (32 << 20)

@@ -443,9 +443,11 @@ struct Plan {
     // per-call tables (256-byte aligned segments): grid views, group table, snapshot times, time
     // step ends, first global cell of each grid (batched ordering)
     size_t b_grids = 0, b_offs = 0, b_gg = 0, b_snap = 0, b_tstep = 0, b_base = 0, tables = 0;
-    // ordering by starting cell: order, rank and bucket [n] each, histogram, tile sums
-    int32_t shift = 0, nbuckets = 0, ntiles = 0;
-    size_t b_order = 0, b_hist = 0, sort_bytes = 0;
+    // ordering by starting cell: order, bucket, super-bucket-ordered buckets and indices [n] each,
+    // the tiles' super-bucket counts, scan tile sums
+    int32_t shift = 0, nbuckets = 0, fine = 0, nsuper = 0, ptiles = 0, ntiles = 0;
+    int64_t ncnt = 0;
+    size_t b_order = 0, b_cnt = 0, sort_bytes = 0;
     // pathline count pass: tile sums of the offset scan
     int64_t scan_ntiles = 0;
     size_t scan_bytes = 0;
@@ -508,10 +510,16 @@ int make_plan(const pt_grid* const* grids, int32_t n_grids, const pt_particles* 
         while ((cells >> shift) >= kMaxBuckets) ++shift;
         P.shift = shift;
         P.nbuckets = (int32_t)(cells >> shift) + 1;
-        P.ntiles = (int32_t)((P.nbuckets + kScanTile - 1) / kScanTile);
+        // about 512 super-buckets (one block each in the second level: two resident per CU) of at
+        // most kFineMax buckets
+        P.fine = (int32_t)std::min<int64_t>(kFineMax, std::max<int64_t>(1, (P.nbuckets + 511) / 512));
+        P.nsuper = (P.nbuckets + P.fine - 1) / P.fine;
+        P.ptiles = (int32_t)((p->n + kSortTile - 1) / kSortTile);
+        P.ncnt = (int64_t)P.nsuper * P.ptiles;
+        P.ntiles = (int32_t)((P.ncnt + kScanTile - 1) / kScanTile);
         P.b_order = align_up(sizeof(int32_t) * (size_t)p->n, 256);
-        P.b_hist = align_up(sizeof(unsigned) * (size_t)P.nbuckets, 256);
-        P.sort_bytes = 3 * P.b_order + P.b_hist + sizeof(unsigned) * (size_t)P.ntiles;
+        P.b_cnt = align_up(sizeof(unsigned) * (size_t)P.ncnt, 256);
+        P.sort_bytes = 4 * P.b_order + P.b_cnt + sizeof(unsigned) * (size_t)P.ntiles;
         P.sort = P.sort_bytes <= sort_budget;
         if (!P.sort && o->sort == PT_SORT_CELL)
             return fail(PT_ERR_UNSUPPORTED, "ordering %lld particles needs %zu bytes of buffer, above the %zu available",
@@ -645,6 +653,10 @@ void bind_params(const Plan& PL, const pt_grid* const* grids, int32_t n_grids, c
     if (PL.sort) {
         SP.nbuckets = PL.nbuckets;
         SP.shift = PL.shift;
+        SP.fine = PL.fine;
+        SP.nsuper = PL.nsuper;
+        SP.ptiles = PL.ptiles;
+        SP.ncnt = PL.ncnt;
         SP.ntiles = PL.ntiles;
         SP.n = p->n;
         SP.cell = p->cell;
@@ -654,10 +666,11 @@ void bind_params(const Plan& PL, const pt_grid* const* grids, int32_t n_grids, c
         SP.group_grid = P.group_grid;
         SP.grid_base = PL.batched ? reinterpret_cast<const int64_t*>(d_tables + (PL.tables - PL.b_base)) : nullptr;
         SP.order = reinterpret_cast<int32_t*>(d_sort);
-        SP.rank = reinterpret_cast<unsigned*>(d_sort + PL.b_order);
-        SP.bucket = reinterpret_cast<unsigned*>(d_sort + 2 * PL.b_order);
-        SP.hist = reinterpret_cast<unsigned*>(d_sort + 3 * PL.b_order);
-        SP.part = reinterpret_cast<unsigned*>(d_sort + 3 * PL.b_order + PL.b_hist);
+        SP.bucket = reinterpret_cast<unsigned*>(d_sort + PL.b_order);
+        SP.sbucket = reinterpret_cast<unsigned*>(d_sort + 2 * PL.b_order);
+        SP.sidx = reinterpret_cast<int32_t*>(d_sort + 3 * PL.b_order);
+        SP.cnt = reinterpret_cast<unsigned*>(d_sort + 4 * PL.b_order);
+        SP.part = reinterpret_cast<unsigned*>(d_sort + 4 * PL.b_order + PL.b_cnt);
         P.order = SP.order;
     }
 }
@@ -685,15 +698,14 @@ void build_seq(const Plan& PL, int64_t n, Counters** cptr, TrackParams* P, SortP
     seq.push(reset_kernel(), dim3(1), dim3(64), cptr, sizeof *cptr);
     if (n > 0) {
         if (PL.sort) {
-            const unsigned nb = (unsigned)((n + 255) / 256);
-            seq.push(sort_clear_kernel(), dim3(std::min(2048u, (unsigned)(SP->nbuckets + 255) / 256)), dim3(256), SP,
-                     sizeof *SP);
-            seq.push(sort_hist_kernel(), dim3(nb), dim3(256), SP, sizeof *SP);
+            const unsigned nt = (unsigned)SP->ptiles;
+            seq.push(sort_tiles_kernel(), dim3(nt), dim3(256), SP, sizeof *SP);
             seq.push(sort_scan_tiles_kernel(), dim3((unsigned)SP->ntiles), dim3(kScanBlock), SP, sizeof *SP);
             seq.push(sort_scan_partials_kernel(), dim3(1), dim3(kScanBlock), SP, sizeof *SP);
             if (SP->ntiles > 1)
                 seq.push(sort_scan_add_kernel(), dim3((unsigned)SP->ntiles), dim3(kScanBlock), SP, sizeof *SP);
-            seq.push(sort_scatter_kernel(), dim3(nb), dim3(256), SP, sizeof *SP);
+            seq.push(sort_spread_kernel(), dim3(nt), dim3(256), SP, sizeof *SP);
+            seq.push(sort_fine_kernel(), dim3((unsigned)SP->nsuper), dim3(kFineBlock), SP, sizeof *SP);
         }
         seq.track_at = seq.n;
         seq.push(PL.fn, dim3(PL.grid), dim3(PL.block), P, sizeof *P, PL.lds);

@@ -173,8 +173,17 @@ struct ScanParams {
     int64_t* head;     // element written 0 before v (path_off[0]); may be null
 };
 
-// Spatial ordering of particles by starting cell (counting sort; one bucket per cell, or per run
-// of 2^shift cells on grids of more than kMaxBuckets cells).
+// Spatial ordering of particles by starting cell (one bucket per cell, or per run of 2^shift
+// cells on grids of more than kMaxBuckets cells), in two levels without global returning
+// atomics: tiles of kSortTile particles count their particles per super-bucket (a run of `fine`
+// consecutive buckets) in LDS, an exclusive scan of those counts (super-bucket-major) places
+// every tile's share of every super-bucket, and one block per super-bucket then orders its range
+// by bucket with an LDS histogram.
+constexpr int kSortTile = 4096;      // particles per tile (256 threads x 16)
+constexpr int kFineMax = 8192;       // buckets per super-bucket at most (a 32 KB LDS histogram)
+constexpr int kMaxSuper = 2048;      // super-buckets at most (kMaxBuckets / kFineMax)
+constexpr int kFineBlock = 1024;     // threads of the per-super-bucket pass (= kScanBlock)
+static_assert(kFineBlock == kScanBlock, "the second level uses the block scan of kScanBlock threads");
 struct SortParams {
     int64_t n;
     const int32_t* cell;
@@ -185,14 +194,22 @@ struct SortParams {
     int32_t n_groups;
     int32_t shift;                  // bucket = global cell id >> shift
     int32_t nbuckets;
-    int32_t ntiles;                 // tiles of kScanTile buckets in the histogram scan
-    unsigned* hist;                 // [nbuckets] counts, then their exclusive prefix sums
-    unsigned* part;                 // [ntiles] tile totals, then their exclusive prefix sums
+    int32_t fine;                   // buckets per super-bucket
+    int32_t nsuper;                 // super-buckets
+    int32_t ptiles;                 // tiles of kSortTile particles
+    int64_t ncnt;                   // nsuper * ptiles
+    int32_t ntiles;                 // tiles of kScanTile entries in the scan of cnt
+    int32_t pad;
+    unsigned* cnt;                  // [nsuper][ptiles] particles of each tile in each super-bucket,
+                                    //   then their exclusive prefix sums (super-bucket-major)
+    unsigned* part;                 // [ntiles] scan tile totals, then their exclusive prefix sums
     unsigned* bucket;               // [n] bucket of each particle
-    unsigned* rank;                 // [n] rank of each particle within its bucket
+    unsigned* sbucket;              // [n] buckets in super-bucket order
+    int32_t* sidx;                  // [n] particle indices in super-bucket order
     int32_t* order;                 // [n]
 };
-constexpr int64_t kMaxBuckets = (int64_t)1 << 24;   // histogram of at most 64 MB
+constexpr int64_t kMaxBuckets = (int64_t)1 << 24;   // one bucket per cell up to 2^24 cells
+static_assert((int64_t)kMaxSuper * kFineMax >= kMaxBuckets, "super-buckets cover every bucket");
 
 enum Precision { P64 = 0, PMIX = 1 };
 enum Layout { L_FACES = 1, L_CELL = 2, L_QUAD = 3 };
@@ -206,12 +223,12 @@ struct KernelKey {
 const void* track_kernel(const KernelKey& k);
 const void* careful_kernel(const KernelKey& k);        // FP64 keys only
 const void* reset_kernel();
-const void* sort_clear_kernel();
-const void* sort_hist_kernel();
+const void* sort_tiles_kernel();
 const void* sort_scan_tiles_kernel();
 const void* sort_scan_partials_kernel();
 const void* sort_scan_add_kernel();
-const void* sort_scatter_kernel();
+const void* sort_spread_kernel();
+const void* sort_fine_kernel();
 const void* scan_tiles_kernel();
 const void* scan_partials_kernel();
 const void* scan_add_kernel();

@@ -719,7 +719,6 @@ __device__ __forceinline__ int32_t step_of(const TrackParams& P, double t) {
 // not tracked by this call, or a final status.
 template <int PREC, int LAYOUT, int OUT, bool BATCHED>
 __device__ int32_t begin(Lane<PREC>& L, const TrackParams& P, const double* snap) {
-    using R = typename Real<PREC>::T;
     const int64_t p = L.pid;
     const int32_t st = P.status[p];
     L.g = 0;
@@ -1437,47 +1436,67 @@ __device__ __forceinline__ int64_t block_scan(int64_t* part, int64_t x) {
     return part[threadIdx.x];
 }
 
-// Spatial ordering: counting sort of the particles by their starting cell.  The order only
-// changes which lanes and dies process which particles, never a result.
+// Spatial ordering: the particles sorted by their starting cell (bucket), in two levels with LDS
+// counters only -- returning atomics on a global histogram run at the L2 atomic units' ~25 G/s
+// on random buckets, which made a one-level counting sort of 1.8e7 particles take 1 ms.  Ranks
+// inside a bucket come from LDS atomics, so the order inside a bucket is arbitrary.  The order
+// only changes which lanes and dies process which particles, never a result.
 
+// The group of particle p: the last group whose first particle is at or before p, searched in
+// [lo, n_groups).
+__device__ __forceinline__ int32_t group_at(const int64_t* offsets, int32_t lo, int32_t n_groups, int64_t p) {
+    int32_t hi = n_groups;   // invariant: offsets[lo] <= p < offsets[hi]
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (offsets[mid] <= p) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Bucket of particle p.  Called with the lanes of a wave on consecutive particles (the first
+// active lane on the lowest): the group of that lane is searched once with wave-uniform values,
+// and only lanes past the end of its group search on their own.
 __device__ __forceinline__ uint32_t sort_bucket(const SortParams& S, int64_t p) {
+    int64_t key = 0;
+    if (S.n_groups > 0) {
+        const int64_t p0 = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)p >> 32)) << 32) |
+                                     __builtin_amdgcn_readfirstlane((uint32_t)p));
+        const int32_t g0 = group_at(S.group_offsets, 0, S.n_groups, p0);
+        const int64_t end0 = (g0 + 1 < S.n_groups) ? S.group_offsets[g0 + 1] : INT64_MAX;
+        const int32_t g = (p < end0) ? g0 : group_at(S.group_offsets, g0 + 1, S.n_groups, p);
+        key = S.grid_base[S.group_grid[g]];
+    }
     const int32_t c = S.cell[p];
     const int32_t st = S.status[p];
     if (c < 0 || (st != ST_ACTIVE && st != ST_MAX_TIME)) return 0u;
-    int64_t key = c;
-    if (S.n_groups > 0) {
-        int32_t lo = 0, hi = S.n_groups;
-        while (hi - lo > 1) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (S.group_offsets[mid] <= p) lo = mid;
-            else hi = mid;
-        }
-        key += S.grid_base[S.group_grid[lo]];
-    }
+    key += c;
     const int64_t b = key >> S.shift;
     return (uint32_t)(b < S.nbuckets ? b : S.nbuckets - 1);
 }
 
-__global__ void __launch_bounds__(256) k_sort_clear(SortParams S) {
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < S.nbuckets;
-         q += (int64_t)gridDim.x * blockDim.x)
-        S.hist[q] = 0u;
-}
-
-// Bucket counts; each particle keeps its bucket and the count its atomic returned (its rank in
-// the bucket), so the scatter needs no second round of atomics.
-__global__ void __launch_bounds__(256) k_sort_hist(SortParams S) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < S.n) {
-        const uint32_t b = sort_bucket(S, p);
-        S.bucket[p] = b;
-        S.rank[p] = atomicAdd(&S.hist[b], 1u);
+// Level 1: each tile of kSortTile particles keeps its particles' buckets and counts them per
+// super-bucket; the counts go to cnt[super][tile].
+__global__ void __launch_bounds__(256) k_sort_tiles(SortParams S) {
+    __shared__ unsigned c[kMaxSuper];
+    for (int q = threadIdx.x; q < S.nsuper; q += 256) c[q] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int q = threadIdx.x; q < kSortTile; q += 256) {
+        const int64_t p = base + q;
+        if (p < S.n) {
+            const uint32_t b = sort_bucket(S, p);
+            S.bucket[p] = b;
+            atomicAdd(&c[b / (uint32_t)S.fine], 1u);
+        }
     }
+    __syncthreads();
+    for (int q = threadIdx.x; q < S.nsuper; q += 256) S.cnt[(int64_t)q * S.ptiles + blockIdx.x] = c[q];
 }
 
-// Exclusive prefix sum of the histogram in three passes: within each tile of kScanTile buckets
-// (tile totals to S.part), over the tile totals (one workgroup), then each tile adds the total of
-// the tiles before it.  Counts and sums stay below n < 2^31.
+// Exclusive prefix sum of the tile counts (super-bucket-major) in three passes: within each tile
+// of kScanTile entries (tile totals to S.part), over the tile totals (one workgroup), then each
+// tile adds the total of the tiles before it.  Counts and sums stay below n < 2^31.
 __global__ void __launch_bounds__(kScanBlock) k_sort_scan_tiles(SortParams S) {
     __shared__ int64_t part[kScanBlock];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
@@ -1485,14 +1504,14 @@ __global__ void __launch_bounds__(kScanBlock) k_sort_scan_tiles(SortParams S) {
     int64_t sum = 0;
 #pragma unroll
     for (int q = 0; q < kScanPer; ++q) {
-        v[q] = (base + q < S.nbuckets) ? S.hist[base + q] : 0u;
+        v[q] = (base + q < S.ncnt) ? S.cnt[base + q] : 0u;
         sum += v[q];
     }
     const int64_t incl = block_scan(part, sum);
     int64_t run = incl - sum;
 #pragma unroll
     for (int q = 0; q < kScanPer; ++q) {
-        if (base + q < S.nbuckets) S.hist[base + q] = (unsigned)run;
+        if (base + q < S.ncnt) S.cnt[base + q] = (unsigned)run;
         run += v[q];
     }
     if (threadIdx.x == kScanBlock - 1) S.part[blockIdx.x] = (unsigned)incl;
@@ -1517,12 +1536,57 @@ __global__ void __launch_bounds__(kScanBlock) k_sort_scan_add(SortParams S) {
     const unsigned add = S.part[blockIdx.x];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     for (int64_t q = threadIdx.x; q < kScanTile; q += kScanBlock)
-        if (base + q < S.nbuckets) S.hist[base + q] += add;
+        if (base + q < S.ncnt) S.cnt[base + q] += add;
 }
 
-__global__ void __launch_bounds__(256) k_sort_scatter(SortParams S) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < S.n) S.order[S.hist[S.bucket[p]] + S.rank[p]] = (int32_t)p;
+// Level 1, placement: each tile writes its particles (index and bucket) from the first slot of
+// its share of each super-bucket on, ranked by LDS atomics.
+__global__ void __launch_bounds__(256) k_sort_spread(SortParams S) {
+    __shared__ unsigned at[kMaxSuper];
+    for (int q = threadIdx.x; q < S.nsuper; q += 256) at[q] = S.cnt[(int64_t)q * S.ptiles + blockIdx.x];
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int q = threadIdx.x; q < kSortTile; q += 256) {
+        const int64_t p = base + q;
+        if (p < S.n) {
+            const uint32_t b = S.bucket[p];
+            const unsigned k = atomicAdd(&at[b / (uint32_t)S.fine], 1u);
+            S.sidx[k] = (int32_t)p;
+            S.sbucket[k] = b;
+        }
+    }
+}
+
+// Level 2: one block per super-bucket orders its range [lo, hi) by bucket: an LDS histogram of
+// its `fine` buckets, the histogram's exclusive prefix sum, then LDS-atomic ranks.
+__global__ void __launch_bounds__(kFineBlock) k_sort_fine(SortParams S) {
+    __shared__ unsigned h[kFineMax];
+    __shared__ int64_t part[kFineBlock];
+    const int s = blockIdx.x;
+    const int64_t lo = S.cnt[(int64_t)s * S.ptiles];
+    const int64_t hi = (s + 1 < S.nsuper) ? (int64_t)S.cnt[(int64_t)(s + 1) * S.ptiles] : S.n;
+    const uint32_t b0 = (uint32_t)s * (uint32_t)S.fine;
+    for (int q = threadIdx.x; q < S.fine; q += kFineBlock) h[q] = 0u;
+    __syncthreads();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kFineBlock) atomicAdd(&h[S.sbucket[i] - b0], 1u);
+    __syncthreads();
+    // exclusive prefix sum of h[0, fine): each thread a run of consecutive buckets
+    const int per = (S.fine + kFineBlock - 1) / kFineBlock;
+    const int q0 = (int)threadIdx.x * per;
+    const int q1 = (q0 + per < S.fine) ? q0 + per : S.fine;
+    int64_t sum = 0;
+    for (int q = q0; q < q1; ++q) sum += h[q];
+    int64_t run = block_scan(part, sum) - sum;
+    for (int q = q0; q < q1; ++q) {
+        const unsigned v = h[q];
+        h[q] = (unsigned)run;
+        run += v;
+    }
+    __syncthreads();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kFineBlock) {
+        const unsigned r = atomicAdd(&h[S.sbucket[i] - b0], 1u);
+        S.order[lo + r] = S.sidx[i];
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1733,12 +1797,12 @@ const void* careful_kernel(const KernelKey& k) {
 const void* reset_kernel() { return reinterpret_cast<const void*>(&k_reset); }
 const void* fill_kernel() { return reinterpret_cast<const void*>(&k_fill); }
 const void* counts_kernel() { return reinterpret_cast<const void*>(&k_counts); }
-const void* sort_clear_kernel() { return reinterpret_cast<const void*>(&k_sort_clear); }
-const void* sort_hist_kernel() { return reinterpret_cast<const void*>(&k_sort_hist); }
+const void* sort_tiles_kernel() { return reinterpret_cast<const void*>(&k_sort_tiles); }
 const void* sort_scan_tiles_kernel() { return reinterpret_cast<const void*>(&k_sort_scan_tiles); }
 const void* sort_scan_partials_kernel() { return reinterpret_cast<const void*>(&k_sort_scan_partials); }
 const void* sort_scan_add_kernel() { return reinterpret_cast<const void*>(&k_sort_scan_add); }
-const void* sort_scatter_kernel() { return reinterpret_cast<const void*>(&k_sort_scatter); }
+const void* sort_spread_kernel() { return reinterpret_cast<const void*>(&k_sort_spread); }
+const void* sort_fine_kernel() { return reinterpret_cast<const void*>(&k_sort_fine); }
 const void* scan_tiles_kernel() { return reinterpret_cast<const void*>(&k_scan_tiles); }
 const void* scan_partials_kernel() { return reinterpret_cast<const void*>(&k_scan_partials); }
 const void* scan_add_kernel() { return reinterpret_cast<const void*>(&k_scan_add); }

@@ -224,3 +224,26 @@ def test_deferred_snapshots_many_times(pt):
     for kw in (dict(schedule=1, layout=2), dict(schedule=2, layout=2), dict(schedule=1, layout=2, block=64)):
         out = gpu_track([g], p, snap_times=snaps, t_max=400.0, **kw)
         compare(out, r, label="1500 snapshots %s" % kw, spacing=(10.0, 10.0, 2.0))
+
+
+def test_ordering_skewed_and_inactive():
+    """The two-level ordering sort on skewed inputs: every particle in one cell (one super-bucket
+    holds them all), and half of the particles already terminated (they all fall in bucket 0).
+    Ordered and unordered runs must be identical: a slot given twice or not at all would leave
+    particles untracked or tracked twice."""
+    require_gpu()
+    g = C.random_grid(40, 30, 6, 1.0, 3.0, 77)
+    rng = np.random.Generator(np.random.PCG64(78))
+    n = 70_001
+    one = H.particles(np.full(n, 17 * 40 + 3), rng.random(n), rng.random(n), rng.random(n))
+    half = C.release(rng, n, g.nx, g.ny, g.nz)
+    half.status[::2] = 1                                   # already at a boundary: not tracked
+    for p in (one, half):
+        ordered = gpu_track([g], p, schedule=1, layout=2, sort=2)
+        plain = gpu_track([g], p, schedule=1, layout=2, sort=1)
+        persistent = gpu_track([g], p, schedule=2, layout=2, sort=2)
+        for k in ("status", "cell", "ncross", "path_hash", "xi", "eta", "zeta", "t", "out_xyz"):
+            assert np.array_equal(ordered[k], plain[k], equal_nan=True), k
+            assert np.array_equal(persistent[k], plain[k], equal_nan=True), k
+        assert ordered["summary"]["crossings"] == plain["summary"]["crossings"] > 0
+    assert (ordered["status"][::2] == 1).all() and (ordered["status"][1::2] != 0).all()

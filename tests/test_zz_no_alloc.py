@@ -134,7 +134,7 @@ def test_noalloc_limits(pt, grids):
         pt.pt_track_noalloc(many, dp, pt.make_opts(), counts, group_offsets=offs,
                             group_grid=np.arange(500, dtype=np.int32))
     assert e.value.code == -7
-    # ordering beyond the scratch: 3e6 particles need 36 MB of ordering buffers
+    # ordering beyond the scratch: 3e6 particles need 48 MB of ordering buffers
     n = 3_000_000
     big = pt.DeviceParticles(*(torch.zeros(n, dtype=t, device="cuda") for t in
                                (torch.int32, torch.float64, torch.float64, torch.float64, torch.float64,
